@@ -1,0 +1,29 @@
+"""Build the FP64 CPU oracle library (test infrastructure only).
+
+The oracle is plain C compiled with gcc; floating-point contraction is off so
+that every expression rounds exactly as written (the voxelization predicates in
+particular must match the HIP library's bit for bit).
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["sc_oracle.c", "mlp_oracle.c"]
+LIB = os.path.join(HERE, "libsc_oracle.so")
+
+
+def build(verbose=False):
+    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    cmd = ["gcc", "-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fno-fast-math",
+           "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-Wextra",
+           "-o", LIB + ".tmp"] + srcs + ["-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)
