@@ -1,0 +1,200 @@
+/*
+ * lbm_abi.h -- C interface of the MI355X two-component Shan-Chen throat
+ * drainage library.
+ *
+ * Method: Montella, Yuan, Chareyre, Gens, "A Hybrid multiphase model based on
+ * lattice Boltzmann method direct simulations".  Each pore throat of a sphere
+ * packing is a small subdomain (Sec. 2.2.2: a triangular prism whose three
+ * walls pass through pairs of sphere centres, closed by inlet and outlet
+ * sections) in which a two-component Shan-Chen lattice Boltzmann model runs
+ * (Sec. 2.1, Eq. 1-5: D3Q19 BGK, moments, cohesion force, non-ideal
+ * equation of state).  The inlet/outlet densities are stepped to raise the
+ * capillary pressure; the entry capillary pressure p_c^e is the largest
+ * pressure the throat holds before the non-wetting phase invades the pore
+ * body (Sec. 2.2.2, definition of p_c^e).
+ *
+ * Conventions shared by every entry point:
+ *  - Lattice units, dx = dt = 1.  Component 0 = wetting (w), 1 = non-wetting
+ *    (nw).  Per-node arrays are laid out x fastest, then y, then z; population
+ *    arrays are [component][direction][z][y][x].
+ *  - D3Q19 direction order: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 =
+ *    (+1,+1,0) (-1,-1,0) (+1,-1,0) (-1,+1,0) (+1,0,+1) (-1,0,-1) (+1,0,-1)
+ *    (-1,0,+1) (0,+1,+1) (0,-1,-1) (0,+1,-1) (0,-1,+1); opposite directions are
+ *    adjacent (odd k <-> k+1).  Weights 1/3, 1/18, 1/36; c_s^2 = 1/3.
+ *  - Node classes (voxelization, node (i,j,k) at integer coordinates): solid
+ *    if (i-cx)^2 + (j-cy)^2 + (k-cz)^2 <= r^2 for any sphere (evaluated in
+ *    FP64 term by term, no fused multiply-add), or, with a prism closure,
+ *    if (i,j) lies outside the triangle of the three prism sphere centres;
+ *    else an inlet bath node (z = 0) or outlet bath node (z = nz-1) when the
+ *    z boundary is LBM_BC_RESERVOIR; else fluid.
+ *  - Every pointer argument is a HOST pointer unless stated otherwise.  The
+ *    caller owns all arrays it passes in and all output arrays; sizes are
+ *    implied by the other arguments.  The library owns handles and the
+ *    device memory behind them.
+ *  - Errors: functions never abort or throw; they return a negative status,
+ *    leave outputs untouched, and record a message for lbm_last_error().
+ *    A positive status is a warning with valid outputs.
+ *  - Device work runs on the handle's stream (lbm_params.stream, a
+ *    hipStream_t, or the null stream).  Calls on one handle must not overlap
+ *    from several host threads.
+ */
+#ifndef LBM_ABI_H
+#define LBM_ABI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)     /* invalid argument                            */
+#define LBM_ENOMEM (-2)     /* device or host allocation failed / too big  */
+#define LBM_EHIP (-3)       /* a HIP runtime call failed                    */
+#define LBM_ENONFINITE (-4) /* the state became non-finite                  */
+#define LBM_ESTATE (-5)     /* call not valid in the handle's state         */
+#define LBM_WNOTCONV 1      /* a ramp point hit its step cap                */
+
+/* boundary kinds, one per axis */
+#define LBM_BC_PERIODIC 0
+#define LBM_BC_WALLS 1      /* nodes beyond the box are solid              */
+#define LBM_BC_RESERVOIR 2  /* z only: z = 0 and z = nz-1 are density baths */
+
+/* node classes reported by lbm_get_types */
+#define LBM_NODE_FLUID 0
+#define LBM_NODE_SOLID 1
+#define LBM_NODE_RES_IN 2
+#define LBM_NODE_RES_OUT 3
+
+/* per-ramp-point status */
+#define LBM_PT_CONVERGED 0
+#define LBM_PT_NOT_CONVERGED 1
+#define LBM_PT_NONFINITE 2
+
+typedef struct {
+  double c[3]; /* centre, lattice units */
+  double r;    /* radius, lattice units */
+} lbm_sphere;
+
+/* Statement of one subdomain run (Sec. 2.1 and 2.2). */
+typedef struct {
+  int nx, ny, nz;            /* box size in nodes, each >= 3                  */
+  int bc[3];                 /* LBM_BC_* for x, y, z (RESERVOIR only for z)   */
+  int n_spheres;             /* >= 0                                          */
+  const lbm_sphere *spheres; /* [n_spheres], host                             */
+  int prism;                 /* 1: solid outside the z-prism over 3 centres   */
+  int prism_ids[3];          /* indices into spheres (used when prism = 1)    */
+  double tau[2];             /* relaxation times (Eq. 1), each > 0.5          */
+  double G;                  /* cohesion strength (Eq. 4-5)                   */
+  double G_ads[2];           /* adhesion strength per component               */
+  double rho_major;          /* majority density of a bulk phase, > 0         */
+  double rho_minor;          /* minority density of a bulk phase, > 0         */
+  double rho_in_nw;          /* nw density of the inlet bath, > 0             */
+  double rho_out_w;          /* w density of the outlet bath, > 0             */
+  const double *rho_init;    /* host [2][nz][ny][nx] initial densities, or
+                                NULL: nw (rho_major) in z <= z_front, w above */
+  int z_front;
+  int probe[3];              /* pore-body probe node; probe[0] < 0: none      */
+  void *stream;              /* hipStream_t or NULL                           */
+} lbm_params;
+
+/* Steady-state test and bisection of one drainage ramp. */
+typedef struct {
+  double tol;          /* stop when |S_w(t) - S_w(t - check_every)| < tol   */
+  int check_every;     /* steps between saturation checks, >= 1             */
+  long long max_steps; /* cap per ramp point (and per bisection run)        */
+  double bisect_rel;   /* stop bisecting when (hi - lo)/hi <= bisect_rel     */
+} lbm_conv;
+
+/* Result of one drainage ramp.  S, steps and status point to caller arrays
+ * of n_pc entries. */
+typedef struct {
+  double pce;          /* entry capillary pressure: midpoint of [lo, hi]   */
+  double pce_lo;       /* largest pressure found stable                     */
+  double pce_hi;       /* smallest pressure found invaded                   */
+  int invaded_at;      /* first invaded ramp index, -1 if none              */
+  int n_bisect;        /* bisection runs made                               */
+  long long total_steps; /* lattice steps run, ramp plus bisection          */
+  double *S;           /* [n_pc] wetting saturation at the end of each point */
+  long long *steps;    /* [n_pc] steps used by each point                   */
+  int *status;         /* [n_pc] LBM_PT_*                                   */
+} lbm_drain_result;
+
+typedef struct lbm_throat *lbm_throat_t;
+
+/* Create a subdomain: voxelize the geometry on the device, allocate two FP32
+ * population buffers (2 x 152 bytes per node) and set the equilibrium state
+ * f = f_eq(rho_init, u = 0) (Eq. 1-3).  *out receives the handle.
+ * Errors: LBM_EINVAL (sizes < 3, tau <= 0.5, non-positive or non-finite
+ * densities, bad prism ids, probe outside the fluid), LBM_ENOMEM, LBM_EHIP. */
+int lbm_throat_init(const lbm_params *p, lbm_throat_t *out);
+
+/* Release a handle and its device memory.  NULL is ignored. */
+void lbm_throat_free(lbm_throat_t h);
+
+/* Advance nsteps >= 0 time steps (Eq. 1: collide toward the component
+ * equilibria with the cohesion (Eq. 4) and adhesion forces, then stream with
+ * half-way bounce-back and bath re-imposition).  Asynchronous on the
+ * handle's stream. */
+int lbm_step(lbm_throat_t h, long long nsteps);
+
+/* Wait for all work queued on the handle's stream. */
+int lbm_sync(lbm_throat_t h);
+
+/* Set the nw density of the inlet bath (takes effect from the next step). */
+int lbm_set_rho_in(lbm_throat_t h, double rho_in_nw);
+
+/* The inlet density that imposes capillary pressure pc: from Eq. 5 with the
+ * minority density fixed, p_in - p_out = c_s^2 (1 + G rho_minor)
+ * (rho_in - rho_out).  Returns NaN for a NULL handle. */
+double lbm_rho_in_for_pc(lbm_throat_t h, double pc);
+
+/* Node count and node classes (host uint8 [nz][ny][nx]). */
+long long lbm_nodes(lbm_throat_t h);
+int lbm_get_types(lbm_throat_t h, unsigned char *types);
+
+/* Pre-collision populations at the current time, unshifted, as FP64:
+ * host [2][19][nz][ny][nx]; zero on solid nodes. Synchronous. */
+int lbm_get_populations(lbm_throat_t h, double *f);
+
+/* Densities rho_w, rho_nw (Eq. 2): host [2][nz][ny][nx]; bath nodes hold the
+ * imposed values, solid nodes zero. Synchronous. */
+int lbm_get_density(lbm_throat_t h, double *rho);
+
+/* FP64 reductions over fluid nodes: masses [2] (Eq. 2 summed) and the
+ * wetting saturation S_w = mean of (phi + phi_b) / (2 phi_b) with
+ * phi = (rho_w - rho_nw)/(rho_w + rho_nw), phi_b = (rho_major - rho_minor) /
+ * (rho_major + rho_minor).  Either output may be NULL. Synchronous. */
+int lbm_reduce(lbm_throat_t h, double *mass2, double *S_w);
+
+/* 1 if rho_nw > rho_w at the probe node, else 0 (invasion test). */
+int lbm_probe_invaded(lbm_throat_t h, int *invaded);
+
+/* Drainage ramp (Sec. 2.2.2): for each pc[i] (strictly increasing), set the
+ * inlet density for pc[i] and run until the saturation changes by less than
+ * c->tol over c->check_every steps (or c->max_steps); record S_w.  At the
+ * first invaded point, bisect between the last stable state and pc[i] on a
+ * copy of the state until the bracket is within c->bisect_rel; the entry
+ * pressure is reported as that bracket (Sec. 2.2.2: p_c^e is the maximum p_c
+ * reached before invasion).  Synchronous.  Returns LBM_WNOTCONV if a point
+ * hit its cap. */
+int lbm_drain_throat(lbm_throat_t h, const double *pc, int n_pc, const lbm_conv *c,
+                     lbm_drain_result *out);
+
+/* Time nsteps steps of the fused update with HIP events on the handle's
+ * stream; *ms receives the elapsed milliseconds.  Synchronous. */
+int lbm_time_steps(lbm_throat_t h, long long nsteps, double *ms);
+
+/* Launch shape of the fused step: tile width tx (32 or 64), tile height ty
+ * (4, 8 or 16), z-segment length lz (>= 1).  0 keeps the current value. */
+int lbm_set_schedule(lbm_throat_t h, int tx, int ty, int lz);
+int lbm_get_schedule(lbm_throat_t h, int *tx, int *ty, int *lz);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

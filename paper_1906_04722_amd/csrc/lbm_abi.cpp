@@ -1,0 +1,723 @@
+// lbm_abi.cpp -- host side of the C interface declared in lbm_abi.h:
+// argument validation, device memory, the step/reduction launches and the
+// drainage ramp with bisection (Montella et al., Sec. 2.2.2).
+#include "lbm_abi.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sc_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+void set_err(const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+#define HIPCHK(call)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      set_err("%s failed: %s", #call, hipGetErrorString(e_));                 \
+      return LBM_EHIP;                                                        \
+    }                                                                         \
+  } while (0)
+
+#define TRY(call)                                                             \
+  do {                                                                        \
+    int r_ = (call);                                                          \
+    if (r_ < 0) return r_;                                                    \
+  } while (0)
+
+constexpr double kCs2 = 1.0 / 3.0;
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+}  // namespace
+
+struct lbm_throat {
+  int nx = 0, ny = 0, nz = 0, per = 0, bc[3] = {0, 0, 0};
+  size_t N = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  float *g[2] = {nullptr, nullptr};  // A/B population buffers
+  int cur = 0;                       // g[cur] holds the current state
+  float *save[2] = {nullptr, nullptr};  // checkpoints used by the ramp
+  uint32_t *mask = nullptr;
+  uint8_t *types_d = nullptr;
+  double *rres_d = nullptr;          // [in/out][component]
+  double *partials = nullptr;
+  int n_partials = 0;
+  double *red_d = nullptr;           // [5]
+  double *red_h = nullptr;           // pinned [5]
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::vector<uint8_t> types;
+  long long n_fluid = 0;
+  long long probe = -1;
+  double tau[2], G, Gads[2], rho_major, rho_minor, rho_in, rho_out;
+  double phib = 1.0;
+  sc::Phys P{};
+  sc::Sched sched{64, 8, 16};
+  long long steps_done = 0;
+};
+
+namespace {
+
+void fill_phys(lbm_throat *h) {
+  sc::Phys &P = h->P;
+  for (int c = 0; c < 2; ++c) {
+    P.tau[c] = (float)h->tau[c];
+    P.itau[c] = (float)(1.0 / h->tau[c]);
+    P.Gads[c] = (float)h->Gads[c];
+  }
+  P.G = (float)h->G;
+  // populations are stored relative to w_k rho_minor: the minority phase,
+  // where populations are smallest, is then held with the most absolute
+  // precision
+  const double ref = h->rho_minor;
+  P.rho_ref = (float)ref;
+  const double rr[2][2] = {{h->rho_minor, h->rho_in}, {h->rho_out, h->rho_minor}};
+  for (int i = 0; i < 2; ++i)
+    for (int c = 0; c < 2; ++c) {
+      P.rres[i][c] = (float)rr[i][c];
+      P.gres[i][c] = (float)(rr[i][c] - ref);
+    }
+}
+
+int upload_rres(lbm_throat *h) {
+  const double rr[4] = {h->rho_minor, h->rho_in, h->rho_out, h->rho_minor};
+  HIPCHK(hipMemcpyAsync(h->rres_d, rr, sizeof rr, hipMemcpyHostToDevice, h->stream));
+  return LBM_OK;
+}
+
+sc::Dom dom(const lbm_throat *h, const float *src, float *dst) {
+  sc::Dom d;
+  d.src = src;
+  d.dst = dst;
+  d.mask = h->mask;
+  d.N = h->N;
+  d.nx = h->nx;
+  d.ny = h->ny;
+  d.nz = h->nz;
+  d.per = h->per;
+  return d;
+}
+
+sc::Sched default_schedule(int nx, int ny, int nz) {
+  sc::Sched s;
+  const int w64 = (nx + 63) / 64 * 64, w32 = (nx + 31) / 32 * 32;
+  s.tx = w32 < w64 ? 32 : 64;
+  s.ty = 8;
+  const long long ntx = (nx + s.tx - 1) / s.tx, nty = (ny + s.ty - 1) / s.ty;
+  long long lz = (ntx * nty * nz + 1023) / 1024;
+  s.lz = (int)std::max(4LL, std::min<long long>(64, lz));
+  return s;
+}
+
+int validate(const lbm_params *p) {
+  if (!p) {
+    set_err("params is NULL");
+    return LBM_EINVAL;
+  }
+  if (p->nx < 3 || p->ny < 3 || p->nz < 3) {
+    set_err("box %d x %d x %d: each side must be >= 3", p->nx, p->ny, p->nz);
+    return LBM_EINVAL;
+  }
+  if ((long long)p->nx * p->ny * p->nz > (1LL << 31)) {
+    set_err("box of %lld nodes exceeds 2^31", (long long)p->nx * p->ny * p->nz);
+    return LBM_EINVAL;
+  }
+  for (int a = 0; a < 3; ++a) {
+    const int b = p->bc[a];
+    const bool ok = b == LBM_BC_PERIODIC || b == LBM_BC_WALLS || (a == 2 && b == LBM_BC_RESERVOIR);
+    if (!ok) {
+      set_err("bc[%d] = %d is not a boundary kind allowed on that axis", a, b);
+      return LBM_EINVAL;
+    }
+  }
+  for (int c = 0; c < 2; ++c)
+    if (!(std::isfinite(p->tau[c]) && p->tau[c] > 0.5)) {
+      set_err("tau[%d] = %g must be finite and > 0.5", c, p->tau[c]);
+      return LBM_EINVAL;
+    }
+  if (!std::isfinite(p->G) || !std::isfinite(p->G_ads[0]) || !std::isfinite(p->G_ads[1])) {
+    set_err("interaction strengths must be finite");
+    return LBM_EINVAL;
+  }
+  if (!finite_pos(p->rho_major) || !finite_pos(p->rho_minor) || !finite_pos(p->rho_in_nw) ||
+      !finite_pos(p->rho_out_w)) {
+    set_err("densities must be finite and > 0");
+    return LBM_EINVAL;
+  }
+  if (p->n_spheres < 0 || (p->n_spheres > 0 && !p->spheres)) {
+    set_err("sphere list invalid");
+    return LBM_EINVAL;
+  }
+  for (int i = 0; i < p->n_spheres; ++i) {
+    const lbm_sphere &s = p->spheres[i];
+    if (!std::isfinite(s.c[0]) || !std::isfinite(s.c[1]) || !std::isfinite(s.c[2]) ||
+        !finite_pos(s.r)) {
+      set_err("sphere %d has a non-finite centre or a non-positive radius", i);
+      return LBM_EINVAL;
+    }
+  }
+  if (p->prism)
+    for (int a = 0; a < 3; ++a)
+      if (p->prism_ids[a] < 0 || p->prism_ids[a] >= p->n_spheres) {
+        set_err("prism sphere id %d out of range", p->prism_ids[a]);
+        return LBM_EINVAL;
+      }
+  return LBM_OK;
+}
+
+void release(lbm_throat *h) {
+  if (!h) return;
+  for (int i = 0; i < 2; ++i) {
+    if (h->g[i]) (void)hipFree(h->g[i]);
+    if (h->save[i]) (void)hipFree(h->save[i]);
+    if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+  }
+  if (h->mask) (void)hipFree(h->mask);
+  if (h->types_d) (void)hipFree(h->types_d);
+  if (h->rres_d) (void)hipFree(h->rres_d);
+  if (h->partials) (void)hipFree(h->partials);
+  if (h->red_d) (void)hipFree(h->red_d);
+  if (h->red_h) (void)hipHostFree(h->red_h);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+int run_steps(lbm_throat *h, long long n) {
+  for (long long i = 0; i < n; ++i) {
+    const sc::Dom d = dom(h, h->g[h->cur], h->g[1 - h->cur]);
+    hipError_t e = sc::launch_step(d, h->P, h->sched, h->stream);
+    if (e != hipSuccess) {
+      set_err("step launch failed: %s", hipGetErrorString(e));
+      return LBM_EHIP;
+    }
+    h->cur = 1 - h->cur;
+  }
+  h->steps_done += n;
+  return LBM_OK;
+}
+
+// FP64 masses, saturation and probe densities of the current state
+int reduce_now(lbm_throat *h, double out[5]) {
+  const sc::Dom d = dom(h, h->g[h->cur], nullptr);
+  HIPCHK(sc::launch_reduce(d, h->P, h->phib, h->probe, h->partials, h->n_partials, h->red_d,
+                           h->stream));
+  HIPCHK(hipMemcpyAsync(h->red_h, h->red_d, 5 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int i = 0; i < 5; ++i) out[i] = h->red_h[i];
+  out[2] = h->n_fluid ? out[2] / (double)h->n_fluid : 0.0;
+  return LBM_OK;
+}
+
+int set_rho_in(lbm_throat *h, double r) {
+  h->rho_in = r;
+  fill_phys(h);
+  return upload_rres(h);
+}
+
+int copy_state(lbm_throat *h, float *dst, const float *src) {
+  HIPCHK(hipMemcpyAsync(dst, src, sizeof(float) * 38 * h->N, hipMemcpyDeviceToDevice, h->stream));
+  return LBM_OK;
+}
+
+// run until |S(t) - S(t - every)| < tol or the cap; returns the point status
+int run_to_steady(lbm_throat *h, const lbm_conv *c, double *S_end, long long *used,
+                  int *invaded) {
+  double r[5];
+  TRY(reduce_now(h, r));
+  double S_old = r[2], S_new = S_old;
+  long long n = 0;
+  int st = LBM_PT_NOT_CONVERGED;
+  for (;;) {
+    TRY(run_steps(h, c->check_every));
+    n += c->check_every;
+    TRY(reduce_now(h, r));
+    S_new = r[2];
+    if (!std::isfinite(S_new)) {
+      st = LBM_PT_NONFINITE;
+      break;
+    }
+    if (std::fabs(S_new - S_old) < c->tol) {
+      st = LBM_PT_CONVERGED;
+      break;
+    }
+    if (n >= c->max_steps) break;
+    S_old = S_new;
+  }
+  *S_end = S_new;
+  *used = n;
+  *invaded = r[4] > r[3] ? 1 : 0;
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
+  g_err.clear();
+  if (!out) {
+    set_err("out is NULL");
+    return LBM_EINVAL;
+  }
+  TRY(validate(p));
+  lbm_throat *h = new (std::nothrow) lbm_throat();
+  if (!h) {
+    set_err("host allocation failed");
+    return LBM_ENOMEM;
+  }
+  h->nx = p->nx;
+  h->ny = p->ny;
+  h->nz = p->nz;
+  h->N = (size_t)p->nx * p->ny * p->nz;
+  for (int a = 0; a < 3; ++a) h->bc[a] = p->bc[a];
+  h->per = (p->bc[0] == LBM_BC_PERIODIC ? 1 : 0) | (p->bc[1] == LBM_BC_PERIODIC ? 2 : 0) |
+           (p->bc[2] == LBM_BC_PERIODIC ? 4 : 0);
+  for (int c = 0; c < 2; ++c) {
+    h->tau[c] = p->tau[c];
+    h->Gads[c] = p->G_ads[c];
+  }
+  h->G = p->G;
+  h->rho_major = p->rho_major;
+  h->rho_minor = p->rho_minor;
+  h->rho_in = p->rho_in_nw;
+  h->rho_out = p->rho_out_w;
+  h->phib = (p->rho_major - p->rho_minor) / (p->rho_major + p->rho_minor);
+  fill_phys(h);
+  h->sched = default_schedule(h->nx, h->ny, h->nz);
+
+  auto fail = [&](int code) {
+    release(h);
+    return code;
+  };
+  // device memory: 2 x 152 B populations + 4 B mask + 1 B class per node
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    set_err("hipMemGetInfo failed");
+    return fail(LBM_EHIP);
+  }
+  const size_t need = h->N * (2 * 38 * sizeof(float) + sizeof(uint32_t) + 1) + (64u << 20);
+  if (need > free_b) {
+    set_err("needs %zu bytes of device memory, %zu free", need, free_b);
+    return fail(LBM_ENOMEM);
+  }
+  if (p->stream) {
+    h->stream = (hipStream_t)p->stream;
+  } else {
+    if (hipStreamCreate(&h->stream) != hipSuccess) {
+      set_err("hipStreamCreate failed");
+      return fail(LBM_EHIP);
+    }
+    h->own_stream = true;
+  }
+  h->n_partials = sc::reduce_blocks(h->N);
+#define ALLOC(ptr, bytes)                                                      \
+  do {                                                                         \
+    if (hipMalloc((void **)&(ptr), (bytes)) != hipSuccess) {                   \
+      set_err("hipMalloc of %zu bytes failed", (size_t)(bytes));               \
+      return fail(LBM_ENOMEM);                                                 \
+    }                                                                          \
+  } while (0)
+  ALLOC(h->g[0], sizeof(float) * 38 * h->N);
+  ALLOC(h->g[1], sizeof(float) * 38 * h->N);
+  ALLOC(h->mask, sizeof(uint32_t) * h->N);
+  ALLOC(h->types_d, h->N);
+  ALLOC(h->rres_d, 4 * sizeof(double));
+  ALLOC(h->partials, sizeof(double) * 3 * h->n_partials);
+  ALLOC(h->red_d, 5 * sizeof(double));
+  if (hipHostMalloc((void **)&h->red_h, 5 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    set_err("hipHostMalloc failed");
+    return fail(LBM_ENOMEM);
+  }
+  for (int i = 0; i < 2; ++i)
+    if (hipEventCreate(&h->ev[i]) != hipSuccess) {
+      set_err("hipEventCreate failed");
+      return fail(LBM_EHIP);
+    }
+
+  // geometry on the device
+  double *sph_d = nullptr, *rho_d = nullptr;
+  const int ns = p->n_spheres;
+  std::vector<double> sph(4 * (size_t)std::max(ns, 1));
+  for (int i = 0; i < ns; ++i) {
+    sph[4 * i + 0] = p->spheres[i].c[0];
+    sph[4 * i + 1] = p->spheres[i].c[1];
+    sph[4 * i + 2] = p->spheres[i].c[2];
+    sph[4 * i + 3] = p->spheres[i].r;
+  }
+  ALLOC(sph_d, sizeof(double) * sph.size());
+  int rc = LBM_OK;
+  do {
+    if (hipMemcpyAsync(sph_d, sph.data(), sizeof(double) * sph.size(), hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess) {
+      rc = LBM_EHIP;
+      break;
+    }
+    const int ids[3] = {p->prism_ids[0], p->prism_ids[1], p->prism_ids[2]};
+    const int safe_ids[3] = {p->prism ? ids[0] : 0, p->prism ? ids[1] : 0, p->prism ? ids[2] : 0};
+    if (sc::launch_voxelize(sph_d, ns, p->prism ? 1 : 0, safe_ids, h->nx, h->ny, h->nz,
+                            p->bc[2] == LBM_BC_RESERVOIR, h->types_d, h->stream) != hipSuccess ||
+        sc::launch_links(h->types_d, h->nx, h->ny, h->nz, h->per, h->mask, h->stream) !=
+            hipSuccess) {
+      rc = LBM_EHIP;
+      break;
+    }
+    h->types.resize(h->N);
+    if (hipMemcpyAsync(h->types.data(), h->types_d, h->N, hipMemcpyDeviceToHost, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+      rc = LBM_EHIP;
+      break;
+    }
+  } while (0);
+  if (rc != LBM_OK) {
+    (void)hipFree(sph_d);
+    set_err("geometry setup failed");
+    return fail(rc);
+  }
+  (void)hipFree(sph_d);
+  long long nf = 0;
+  for (size_t n = 0; n < h->N; ++n) nf += h->types[n] == sc::kFluid;
+  h->n_fluid = nf;
+
+  if (p->probe[0] >= 0) {
+    if (p->probe[0] >= h->nx || p->probe[1] < 0 || p->probe[1] >= h->ny || p->probe[2] < 0 ||
+        p->probe[2] >= h->nz) {
+      set_err("probe node outside the box");
+      return fail(LBM_EINVAL);
+    }
+    h->probe = (long long)p->probe[0] +
+               (long long)h->nx * ((long long)p->probe[1] + (long long)h->ny * p->probe[2]);
+    if (h->types[h->probe] != sc::kFluid) {
+      set_err("probe node is not a fluid node");
+      return fail(LBM_EINVAL);
+    }
+  }
+  if (p->rho_init) {
+    for (int c = 0; c < 2; ++c)
+      for (size_t n = 0; n < h->N; ++n)
+        if (h->types[n] == sc::kFluid && !finite_pos(p->rho_init[c * h->N + n])) {
+          set_err("rho_init is not finite and positive on fluid node %zu", n);
+          return fail(LBM_EINVAL);
+        }
+    ALLOC(rho_d, sizeof(double) * 2 * h->N);
+    if (hipMemcpyAsync(rho_d, p->rho_init, sizeof(double) * 2 * h->N, hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess) {
+      (void)hipFree(rho_d);
+      set_err("rho_init upload failed");
+      return fail(LBM_EHIP);
+    }
+  }
+  if (upload_rres(h) != LBM_OK) {
+    if (rho_d) (void)hipFree(rho_d);
+    return fail(LBM_EHIP);
+  }
+  const sc::Dom d = dom(h, nullptr, nullptr);
+  hipError_t e = sc::launch_init(d, h->P, rho_d, h->rho_major, h->rho_minor, p->z_front, h->rres_d,
+                                 h->g[0], h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->g[1], 0, sizeof(float) * 38 * h->N, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (rho_d) (void)hipFree(rho_d);
+  if (e != hipSuccess) {
+    set_err("initial state failed: %s", hipGetErrorString(e));
+    return fail(LBM_EHIP);
+  }
+  h->cur = 0;
+  *out = h;
+  return LBM_OK;
+#undef ALLOC
+}
+
+void lbm_throat_free(lbm_throat_t h) { release(h); }
+
+int lbm_step(lbm_throat_t h, long long nsteps) {
+  if (!h || nsteps < 0) {
+    set_err("lbm_step: bad handle or negative step count");
+    return LBM_EINVAL;
+  }
+  return run_steps(h, nsteps);
+}
+
+int lbm_sync(lbm_throat_t h) {
+  if (!h) {
+    set_err("NULL handle");
+    return LBM_EINVAL;
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_set_rho_in(lbm_throat_t h, double r) {
+  if (!h || !finite_pos(r)) {
+    set_err("lbm_set_rho_in: bad handle or density");
+    return LBM_EINVAL;
+  }
+  return set_rho_in(h, r);
+}
+
+double lbm_rho_in_for_pc(lbm_throat_t h, double pc) {
+  if (!h) return NAN;
+  return h->rho_out + pc / (kCs2 * (1.0 + h->G * h->rho_minor));
+}
+
+long long lbm_nodes(lbm_throat_t h) { return h ? (long long)h->N : -1; }
+
+int lbm_get_types(lbm_throat_t h, unsigned char *types) {
+  if (!h || !types) {
+    set_err("lbm_get_types: NULL argument");
+    return LBM_EINVAL;
+  }
+  std::memcpy(types, h->types.data(), h->N);
+  return LBM_OK;
+}
+
+int lbm_get_populations(lbm_throat_t h, double *f) {
+  if (!h || !f) {
+    set_err("lbm_get_populations: NULL argument");
+    return LBM_EINVAL;
+  }
+  double *fd = nullptr;
+  if (hipMalloc((void **)&fd, sizeof(double) * 38 * h->N) != hipSuccess) {
+    set_err("hipMalloc for the export failed");
+    return LBM_ENOMEM;
+  }
+  const sc::Dom d = dom(h, h->g[h->cur], nullptr);
+  hipError_t e = sc::launch_export(d, h->P, h->rres_d, fd, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(f, fd, sizeof(double) * 38 * h->N, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(fd);
+  if (e != hipSuccess) {
+    set_err("export failed: %s", hipGetErrorString(e));
+    return LBM_EHIP;
+  }
+  return LBM_OK;
+}
+
+int lbm_get_density(lbm_throat_t h, double *rho) {
+  if (!h || !rho) {
+    set_err("lbm_get_density: NULL argument");
+    return LBM_EINVAL;
+  }
+  double *rd = nullptr;
+  if (hipMalloc((void **)&rd, sizeof(double) * 2 * h->N) != hipSuccess) {
+    set_err("hipMalloc for the density read-back failed");
+    return LBM_ENOMEM;
+  }
+  const sc::Dom d = dom(h, h->g[h->cur], nullptr);
+  hipError_t e = sc::launch_density(d, h->P, h->rres_d, rd, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(rho, rd, sizeof(double) * 2 * h->N, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(rd);
+  if (e != hipSuccess) {
+    set_err("density read-back failed: %s", hipGetErrorString(e));
+    return LBM_EHIP;
+  }
+  return LBM_OK;
+}
+
+int lbm_reduce(lbm_throat_t h, double *mass2, double *S_w) {
+  if (!h) {
+    set_err("NULL handle");
+    return LBM_EINVAL;
+  }
+  double r[5];
+  TRY(reduce_now(h, r));
+  if (mass2) {
+    mass2[0] = r[0];
+    mass2[1] = r[1];
+  }
+  if (S_w) *S_w = r[2];
+  return LBM_OK;
+}
+
+int lbm_probe_invaded(lbm_throat_t h, int *invaded) {
+  if (!h || !invaded) {
+    set_err("NULL argument");
+    return LBM_EINVAL;
+  }
+  if (h->probe < 0) {
+    set_err("the handle has no probe node");
+    return LBM_ESTATE;
+  }
+  double r[5];
+  TRY(reduce_now(h, r));
+  *invaded = r[4] > r[3] ? 1 : 0;
+  return LBM_OK;
+}
+
+int lbm_drain_throat(lbm_throat_t h, const double *pc, int n_pc, const lbm_conv *c,
+                     lbm_drain_result *out) {
+  if (!h || !pc || n_pc < 1 || !c || !out || !out->S || !out->steps || !out->status) {
+    set_err("lbm_drain_throat: NULL argument or n_pc < 1");
+    return LBM_EINVAL;
+  }
+  if (!(c->tol > 0) || c->check_every < 1 || c->max_steps < c->check_every ||
+      !(c->bisect_rel > 0)) {
+    set_err("lbm_drain_throat: invalid convergence settings");
+    return LBM_EINVAL;
+  }
+  if (h->probe < 0) {
+    set_err("lbm_drain_throat needs a probe node");
+    return LBM_ESTATE;
+  }
+  for (int i = 0; i < n_pc; ++i) {
+    if (!std::isfinite(pc[i]) || !(lbm_rho_in_for_pc(h, pc[i]) > 0) ||
+        (i > 0 && !(pc[i] > pc[i - 1]))) {
+      set_err("pc must be finite, strictly increasing and give a positive inlet density");
+      return LBM_EINVAL;
+    }
+  }
+  for (int i = 0; i < 2; ++i)
+    if (!h->save[i] && hipMalloc((void **)&h->save[i], sizeof(float) * 38 * h->N) != hipSuccess) {
+      set_err("hipMalloc of a ramp checkpoint failed");
+      return LBM_ENOMEM;
+    }
+  float *stable = h->save[0], *mainsave = h->save[1];
+  std::vector<double> S(n_pc);
+  std::vector<long long> steps(n_pc);
+  std::vector<int> status(n_pc);
+  TRY(copy_state(h, stable, h->g[h->cur]));
+  double stable_pc = 0.0, stable_rho_in = h->rho_in;
+  int inv_at = -1, n_bis = 0;
+  double lo = NAN, hi = NAN;
+  long long total = 0;
+  bool warn = false;
+  for (int i = 0; i < n_pc; ++i) {
+    TRY(set_rho_in(h, lbm_rho_in_for_pc(h, pc[i])));
+    int inv = 0;
+    const int st = run_to_steady(h, c, &S[i], &steps[i], &inv);
+    if (st < 0) return st;
+    status[i] = st;
+    total += steps[i];
+    if (st == LBM_PT_NONFINITE) {
+      set_err("state became non-finite at ramp point %d", i);
+      return LBM_ENONFINITE;
+    }
+    warn |= st == LBM_PT_NOT_CONVERGED;
+    if (!inv) {
+      TRY(copy_state(h, stable, h->g[h->cur]));
+      stable_pc = pc[i];
+      stable_rho_in = h->rho_in;
+      continue;
+    }
+    if (inv_at >= 0) continue;
+    inv_at = i;
+    lo = i == 0 ? 0.0 : stable_pc;
+    hi = pc[i];
+    // bisect on copies of the last stable state; the ramp state is kept aside
+    const double main_rho_in = h->rho_in;
+    TRY(copy_state(h, mainsave, h->g[h->cur]));
+    while ((hi - lo) / hi > c->bisect_rel) {
+      const double mid = 0.5 * (lo + hi);
+      TRY(copy_state(h, h->g[h->cur], stable));
+      TRY(set_rho_in(h, lbm_rho_in_for_pc(h, mid)));
+      double Sm;
+      long long nm;
+      int invm = 0;
+      const int sm = run_to_steady(h, c, &Sm, &nm, &invm);
+      if (sm < 0) return sm;
+      total += nm;
+      ++n_bis;
+      if (sm == LBM_PT_NONFINITE) {
+        set_err("state became non-finite while bisecting");
+        return LBM_ENONFINITE;
+      }
+      if (invm) {
+        hi = mid;
+      } else {
+        lo = mid;
+        TRY(copy_state(h, stable, h->g[h->cur]));
+        stable_rho_in = h->rho_in;
+      }
+    }
+    TRY(copy_state(h, h->g[h->cur], mainsave));
+    TRY(set_rho_in(h, main_rho_in));
+  }
+  (void)stable_rho_in;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int i = 0; i < n_pc; ++i) {
+    out->S[i] = S[i];
+    out->steps[i] = steps[i];
+    out->status[i] = status[i];
+  }
+  out->invaded_at = inv_at;
+  out->n_bisect = n_bis;
+  out->total_steps = total;
+  if (inv_at < 0) {
+    out->pce_lo = pc[n_pc - 1];
+    out->pce = NAN;
+    out->pce_hi = INFINITY;
+  } else {
+    out->pce_lo = lo;
+    out->pce_hi = hi;
+    out->pce = 0.5 * (lo + hi);
+  }
+  return warn ? LBM_WNOTCONV : LBM_OK;
+}
+
+int lbm_time_steps(lbm_throat_t h, long long nsteps, double *ms) {
+  if (!h || nsteps < 0 || !ms) {
+    set_err("lbm_time_steps: bad argument");
+    return LBM_EINVAL;
+  }
+  HIPCHK(hipEventRecord(h->ev[0], h->stream));
+  TRY(run_steps(h, nsteps));
+  HIPCHK(hipEventRecord(h->ev[1], h->stream));
+  HIPCHK(hipEventSynchronize(h->ev[1]));
+  float t = 0.f;
+  HIPCHK(hipEventElapsedTime(&t, h->ev[0], h->ev[1]));
+  *ms = t;
+  return LBM_OK;
+}
+
+int lbm_set_schedule(lbm_throat_t h, int tx, int ty, int lz) {
+  if (!h) {
+    set_err("NULL handle");
+    return LBM_EINVAL;
+  }
+  sc::Sched s = h->sched;
+  if (tx) s.tx = tx;
+  if (ty) s.ty = ty;
+  if (lz) s.lz = lz;
+  if (!sc::schedule_valid(s)) {
+    set_err("schedule (%d, %d, %d) not supported", s.tx, s.ty, s.lz);
+    return LBM_EINVAL;
+  }
+  h->sched = s;
+  return LBM_OK;
+}
+
+int lbm_get_schedule(lbm_throat_t h, int *tx, int *ty, int *lz) {
+  if (!h) {
+    set_err("NULL handle");
+    return LBM_EINVAL;
+  }
+  if (tx) *tx = h->sched.tx;
+  if (ty) *ty = h->sched.ty;
+  if (lz) *lz = h->sched.lz;
+  return LBM_OK;
+}
+
+}  // extern "C"

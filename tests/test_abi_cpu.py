@@ -1,0 +1,61 @@
+"""Host-side checks of the HIP library that need no GPU: it loads, exports
+every entry point that include/lbm_abi.h declares, and the Python binding
+names the same set."""
+import ctypes
+import os
+import re
+
+from paper_1906_04722_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_entry_points():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", fn)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", src))
+    return names
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared_entry_points()
+    for must in ("lbm_throat_init", "lbm_step", "lbm_drain_throat", "lbm_throat_free",
+                 "lbm_get_populations", "lbm_reduce", "lbm_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(lbm.LIB_PATH)
+    missing = [n for n in sorted(declared_entry_points()) if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    assert declared_entry_points() == set(lbm.SIGNATURES)
+
+
+def test_invalid_arguments_rejected_without_gpu_work():
+    """Validation runs before any device call: bad sizes and relaxation
+    times are refused with LBM_EINVAL and a message."""
+    L = lbm.lib()
+    import synth
+    p = synth.c1_problem()
+    P, keep = lbm.make_params(p)
+    P.tau[0] = 0.5
+    h = ctypes.c_void_p()
+    rc = L.lbm_throat_init(ctypes.byref(P), ctypes.byref(h))
+    assert rc == lbm.LBM_EINVAL
+    assert b"tau" in L.lbm_last_error()
+    P.tau[0] = 1.0
+    P.nx = 2
+    assert L.lbm_throat_init(ctypes.byref(P), ctypes.byref(h)) == lbm.LBM_EINVAL
+    P.nx = 40
+    P.bc[0] = lbm.LBM_BC_RESERVOIR
+    assert L.lbm_throat_init(ctypes.byref(P), ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
+    L.lbm_throat_free(None)
+    del keep

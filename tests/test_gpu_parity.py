@@ -1,0 +1,157 @@
+"""GPU (HIP, FP32 shifted populations, FP64 arithmetic) against the FP64
+oracle on the same seeded inputs, through the C interface.
+
+Bars: node classes bit for bit; pre-collision populations within 1e-5
+relative after 200 steps on the 40^3 throat (plain relative error: every
+population there is >= 6e-4).  Where a sharp initial interface meets a wall,
+single populations pass through zero, so the other cases measure each
+population's error against its natural scale w_k rho_s(x) (the equilibrium
+value at rest) with the same 1e-5 bar.  FP64 reductions within 1e-6."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import BC_PERIODIC, BC_RESERVOIR, BC_WALLS, Problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _lbm():
+    from paper_1906_04722_amd import lbm
+    return lbm
+
+
+W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def _rel_err(fg, fo, types):
+    live = types != 1
+    a = fg[:, :, live]
+    b = fo[:, :, live]
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+def _scaled_err(fg, fo, types):
+    """max |f_gpu - f_orc| / (w_k rho_s) over live nodes, rho_s = sum_k f_orc"""
+    live = types != 1
+    a = fg[:, :, live]
+    b = fo[:, :, live]
+    rho = b.sum(axis=1, keepdims=True)
+    return float(np.max(np.abs(a - b) / (W[None, :, None] * rho)))
+
+
+def _ragged_problem(seed=4):
+    nx, ny, nz = 70, 37, 29
+    sph = np.array([[20.0, 14.0, 12.0, 7.5], [52.3, 25.1, 15.2, 6.2], [33.0, 30.5, 22.0, 4.0]])
+    rho0 = synth.layered_density(nx, ny, nz, 6, 2.0, 0.0609883, seed=seed, amp=1e-3)
+    return Problem(nx=nx, ny=ny, nz=nz, bc=(BC_WALLS, BC_PERIODIC, BC_RESERVOIR), spheres=sph,
+                   tau=(1.0, 1.2), rho_init=rho0, rho_in_nw=2.03, probe=(35, 20, 20))
+
+
+def _periodic_problem(seed=5):
+    nx, ny, nz = 33, 18, 20
+    rho0 = synth.droplet_density(nx, ny, nz, (16.0, 9.0, 10.0), 6.0, 2.0, 0.0609883, seed=seed,
+                                 amp=1e-3)
+    return Problem(nx=nx, ny=ny, nz=nz, bc=(BC_PERIODIC,) * 3, tau=(0.9, 1.1),
+                   spheres=np.array([[3.0, 3.0, 3.0, 2.5]]), rho_init=rho0)
+
+
+def test_node_classes_bitwise():
+    lbm = _lbm()
+    for p in (synth.c1_problem(), synth.c2_problem(n=48, mean_r=16.0), _ragged_problem(),
+              _periodic_problem()):
+        o = oracle.Oracle(p)
+        g = lbm.Throat(p)
+        assert np.array_equal(o.types(), g.types())
+
+
+def test_c1_populations_after_200_steps():
+    lbm = _lbm()
+    p = synth.c1_problem(seed=1)
+    o = oracle.Oracle(p)
+    g = lbm.Throat(p)
+    t = o.types()
+    assert _rel_err(g.f(), o.f(), t) < 1e-6  # initial state
+    o.step(200)
+    g.step(200)
+    err = _rel_err(g.f(), o.f(), t)
+    print("c1 max rel err after 200 steps", err)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("maker", [_ragged_problem, _periodic_problem])
+def test_populations_ragged_and_periodic(maker):
+    lbm = _lbm()
+    p = maker()
+    o = oracle.Oracle(p)
+    g = lbm.Throat(p)
+    t = o.types()
+    o.step(200)
+    g.step(200)
+    err = _scaled_err(g.f(), o.f(), t)
+    print(maker.__name__, "max scaled err after 200 steps", err)
+    assert err <= 1e-5
+
+
+def test_schedules_agree_bitwise():
+    """The tiling of the fused step does not change any result bit: every
+    node's update reads the same values in the same order whatever the tile."""
+    lbm = _lbm()
+    p = _ragged_problem()
+    ref = None
+    for tx, ty, lz in [(64, 8, 16), (32, 4, 3), (32, 16, 29), (64, 4, 1), (32, 8, 7)]:
+        g = lbm.Throat(p)
+        g.set_schedule(tx, ty, lz)
+        g.step(30)
+        f = g.f()
+        if ref is None:
+            ref = f
+        else:
+            assert np.array_equal(f, ref), (tx, ty, lz)
+
+
+def test_rerun_is_bitwise_identical():
+    lbm = _lbm()
+    p = _periodic_problem()
+    a = lbm.Throat(p)
+    a.step(40)
+    b = lbm.Throat(p)
+    b.step(40)
+    assert np.array_equal(a.f(), b.f())
+    (ma, Sa), (mb, Sb) = a.reduce(), b.reduce()
+    assert np.array_equal(ma, mb) and Sa == Sb
+
+
+def test_reductions_and_density():
+    lbm = _lbm()
+    p = _ragged_problem()
+    o = oracle.Oracle(p)
+    g = lbm.Throat(p)
+    o.step(60)
+    g.step(60)
+    mo, So, _ = o.reduce()
+    mg, Sg = g.reduce()
+    np.testing.assert_allclose(mg, mo, rtol=1e-6)
+    assert abs(Sg - So) < 1e-6
+    t = o.types()
+    live = t != 1
+    np.testing.assert_allclose(g.density()[:, live], o.density()[:, live], rtol=1e-6)
+    assert g.probe_invaded() == o.probe_invaded()
+
+
+def test_closed_box_mass_drift_fp32():
+    """Per-component mass in a closed box: exact in the method, FP32 rounding
+    drift only on the GPU (reported, bounded)."""
+    lbm = _lbm()
+    n = 24
+    sph = np.array([[6.0, 7.0, 9.0, 4.5], [17.0, 15.0, 12.0, 4.7]])
+    rho0 = synth.droplet_density(n, n, n, (12, 12, 12), 6.0, 2.0, 0.0609883, seed=3, amp=1e-3)
+    p = Problem(nx=n, ny=n, nz=n, bc=(BC_WALLS,) * 3, spheres=sph, rho_init=rho0)
+    g = lbm.Throat(p)
+    m0, _ = g.reduce()
+    g.step(1000)
+    m1, _ = g.reduce()
+    drift = np.abs(m1 - m0) / m0
+    print("FP32 relative mass drift over 1000 steps", drift)
+    assert drift.max() < 1e-5
