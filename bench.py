@@ -1,0 +1,188 @@
+"""Benchmark of the Shan-Chen throat drainage hot path on one MI355X.
+
+One "step" is one full pass of the hot path over the 96^3 single-throat
+workload: voxelize the four spheres and the prism closure, set the initial
+state, then run the drainage ramp of 20 capillary pressures, each to steady
+state (|dS_w| < 1e-6 over 100 steps, capped), with bisection of the entry
+pressure.  Inputs are seeded and synthetic; the HIP library does all the work.
+
+Prints one JSON line: lattice MLUPS over the whole job, the roofline of the
+fused step kernel (HIP-event timed launches inside the ramp), the FP64 CPU
+oracle timed on this host beside it, and an HBM-bound 512^3 measurement of the
+same kernel.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import synth  # noqa: E402
+from paper_1906_04722_amd import lbm  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, vendor figure
+BYTES_PER_FLUID_NODE = 304   # 2 components x 19 FP32 populations, read + write
+GAMMA = 0.196                # interfacial tension of the model at G = 0.9 (Laplace fit)
+N_PC = 20
+CONV = dict(tol=1e-6, check_every=100, max_steps=20000, bisect_rel=0.005)
+KERNEL_SRC = os.path.join(ROOT, "paper_1906_04722_amd", "csrc", "sc_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_c2_96_traffic.txt")
+
+
+def kernel_sha():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per step launch from the committed counter summary, if it was
+    taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_sha") != kernel_sha():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def c2_workload():
+    p = synth.c2_problem()
+    r_ins, _ = synth.throat_incircle(p.spheres)
+    pcs = synth.pc_ramp(GAMMA, r_ins, N_PC)
+    return p, pcs
+
+
+def one_drain(p, pcs):
+    g = lbm.Throat(p)
+    g.step_timer(1)
+    out = g.drain(pcs, **CONV)
+    ms, launches = g.step_timer(-1)
+    n_fluid = int((g.types() == lbm.LBM_NODE_FLUID).sum())
+    g.close()
+    return out, ms, launches, n_fluid
+
+
+def cpu_baseline(p, budget_s=12.0):
+    """The FP64 oracle (test infrastructure) on this host's cores: a bounded
+    sample of the same workload (the same throat at a fixed inlet density,
+    whole steps until the time budget is used)."""
+    import oracle
+    o = oracle.Oracle(p)
+    o.step(2)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        o.step(20)
+        n += 20
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(p.n_nodes * n / dt / 1e6, 2), "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": f"96^3 throat, {n} FP64 steps at a fixed inlet density ({dt:.1f} s)"}
+
+
+def dense_512(steps=10):
+    """The same fused step on a 512^3 periodic fluid box (HBM-bound shape)."""
+    n = 512
+    p = synth.Problem(nx=n, ny=n, nz=n, bc=(synth.BC_PERIODIC,) * 3, z_front=n // 2,
+                      G_ads=(0.0, 0.0))
+    g = lbm.Throat(p)
+    g.step(2)
+    g.sync()
+    ms = g.time_steps(steps) / steps
+    g.close()
+    nodes = n ** 3
+    gbs = nodes * BYTES_PER_FLUID_NODE / (ms * 1e-3) / 1e9
+    return {"workload": "512^3 periodic fluid box", "ms_per_step": round(ms, 4),
+            "MLUPS": round(nodes / ms / 1e3, 1), "achieved_GBps": round(gbs, 1),
+            "peak_GBps": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported "
+              "(throat batches shard with no communication; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    p, pcs = c2_workload()
+    for _ in range(a.warmup):
+        one_drain(p, pcs)
+
+    t0 = time.perf_counter()
+    results = [one_drain(p, pcs) for _ in range(a.steps)]
+    dt = time.perf_counter() - t0
+
+    total_steps = sum(r[0]["total_steps"] for r in results)
+    node_updates = p.n_nodes * total_steps
+    n_fluid = results[0][3]
+    mlups = node_updates / dt / 1e6
+    k_ms = sum(r[1] for r in results)
+    k_launches = sum(r[2] for r in results)
+    avg_launch_s = k_ms * 1e-3 / max(k_launches, 1)
+    alg_bytes = n_fluid * BYTES_PER_FLUID_NODE
+    achieved = alg_bytes / avg_launch_s / 1e9
+    out = results[-1][0]
+
+    line = {
+        "metric": "MLUPS (Shan-Chen two-component D3Q19, 96^3 throat drainage ramp)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(dt / a.steps * 1e3, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "storage_dtype": "f32",
+        "data": "synthetic (seeded)",
+        "config": {"workload": "96^3 single pore throat: 4 spheres, lognormal radii (mean 32 lu, "
+                               "sigma 0.15) on a jittered tetrahedron, prism closure, 20-point "
+                               "drainage ramp to steady state + bisection of p_c^e",
+                   "nx": p.nx, "ny": p.ny, "nz": p.nz, "n_pc": N_PC,
+                   "fluid_nodes": n_fluid, "tol": CONV["tol"],
+                   "check_every": CONV["check_every"], "max_steps_per_point": CONV["max_steps"]},
+        "fluid_MLUPS": round(n_fluid * total_steps / dt / 1e6, 1),
+        "lattice_steps_per_drain": total_steps // a.steps,
+        "pce": lbm.nan_safe(out["pce"]),
+        "pce_bracket": [out["pce_lo"], lbm.nan_safe(out["pce_hi"])],
+        "drainage_curve": {"pc": [round(float(x), 6) for x in pcs],
+                           "S_w": [round(float(x), 6) for x in out["S"]]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": read_traffic(),
+                     "kernel": "k_step (fused pull + moments + cohesion/adhesion + BGK)",
+                     "launches": k_launches, "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                     "alg_bytes_per_launch": alg_bytes},
+    }
+    line["copy_probe_GBps"] = round(lbm.bw_probe(4 << 30, 10), 1)
+    if not a.no_dense:
+        line["dense_512"] = dense_512()
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -79,7 +79,7 @@ typedef struct {
 
 /* Statement of one subdomain run (Sec. 2.1 and 2.2). */
 typedef struct {
-  int nx, ny, nz;            /* box size in nodes, each >= 3                  */
+  int nx, ny, nz;            /* box size in nodes, each >= 3, product < 2^29  */
   int bc[3];                 /* LBM_BC_* for x, y, z (RESERVOIR only for z)   */
   int n_spheres;             /* >= 0                                          */
   const lbm_sphere *spheres; /* [n_spheres], host                             */
@@ -186,10 +186,24 @@ int lbm_drain_throat(lbm_throat_t h, const double *pc, int n_pc, const lbm_conv 
  * stream; *ms receives the elapsed milliseconds.  Synchronous. */
 int lbm_time_steps(lbm_throat_t h, long long nsteps, double *ms);
 
-/* Launch shape of the fused step: tile width tx (32 or 64), tile height ty
- * (4, 8 or 16), z-segment length lz (>= 1).  0 keeps the current value. */
+/* Event timing of the fused-step launches made inside lbm_drain_throat:
+ * HIP events bracket each chunk of back-to-back step launches on the
+ * handle's stream.  Returns the accumulated milliseconds and launch count
+ * (either output may be NULL); enable = 1 / 0 resets the totals and turns
+ * timing on / off, enable = -1 only reads. */
+int lbm_step_timer(lbm_throat_t h, int enable, double *total_ms, long long *launches);
+
+/* Launch shape of the fused step: tile (tx, ty) in {(32, 4), (32, 8),
+ * (64, 4)}, z-segment length lz (>= 1).  0 keeps the current value. */
 int lbm_set_schedule(lbm_throat_t h, int tx, int ty, int lz);
 int lbm_get_schedule(lbm_throat_t h, int *tx, int *ty, int *lz);
+
+/* Stream-copy probe of the achievable HBM bandwidth (the measured roofline
+ * denominator beside the 8 TB/s specification): copies `bytes` (>= 1 MiB)
+ * between two device buffers `reps` times on the null stream and returns the
+ * read + write rate in GB/s.  Allocates and frees 2 x bytes of device memory.
+ * Synchronous. */
+int lbm_bw_probe(size_t bytes, int reps, double *gbps);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *lbm_last_error(void);

@@ -71,8 +71,13 @@ struct lbm_throat {
   double tau[2], G, Gads[2], rho_major, rho_minor, rho_in, rho_out;
   double phib = 1.0;
   sc::Phys P{};
-  sc::Sched sched{64, 8, 16};
+  sc::Sched sched{64, 4, 16};
   long long steps_done = 0;
+  // event-timed step launches inside the drainage ramp
+  hipEvent_t tev[2] = {nullptr, nullptr};
+  bool timing = false;
+  double timed_ms = 0.0;
+  long long timed_launches = 0;
 };
 
 namespace {
@@ -121,7 +126,7 @@ sc::Sched default_schedule(int nx, int ny, int nz) {
   sc::Sched s;
   const int w64 = (nx + 63) / 64 * 64, w32 = (nx + 31) / 32 * 32;
   s.tx = w32 < w64 ? 32 : 64;
-  s.ty = 8;
+  s.ty = s.tx == 64 ? 4 : 8;
   const long long ntx = (nx + s.tx - 1) / s.tx, nty = (ny + s.ty - 1) / s.ty;
   long long lz = (ntx * nty * nz + 1023) / 1024;
   s.lz = (int)std::max(4LL, std::min<long long>(64, lz));
@@ -137,8 +142,9 @@ int validate(const lbm_params *p) {
     set_err("box %d x %d x %d: each side must be >= 3", p->nx, p->ny, p->nz);
     return LBM_EINVAL;
   }
-  if ((long long)p->nx * p->ny * p->nz > (1LL << 31)) {
-    set_err("box of %lld nodes exceeds 2^31", (long long)p->nx * p->ny * p->nz);
+  if ((long long)p->nx * p->ny * p->nz >= (1LL << 29)) {
+    set_err("box of %lld nodes: at most 2^29 - 1 nodes per subdomain",
+            (long long)p->nx * p->ny * p->nz);
     return LBM_EINVAL;
   }
   for (int a = 0; a < 3; ++a) {
@@ -190,6 +196,7 @@ void release(lbm_throat *h) {
     if (h->g[i]) (void)hipFree(h->g[i]);
     if (h->save[i]) (void)hipFree(h->save[i]);
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+    if (h->tev[i]) (void)hipEventDestroy(h->tev[i]);
   }
   if (h->mask) (void)hipFree(h->mask);
   if (h->types_d) (void)hipFree(h->types_d);
@@ -247,9 +254,17 @@ int run_to_steady(lbm_throat *h, const lbm_conv *c, double *S_end, long long *us
   long long n = 0;
   int st = LBM_PT_NOT_CONVERGED;
   for (;;) {
+    if (h->timing) HIPCHK(hipEventRecord(h->tev[0], h->stream));
     TRY(run_steps(h, c->check_every));
+    if (h->timing) HIPCHK(hipEventRecord(h->tev[1], h->stream));
     n += c->check_every;
     TRY(reduce_now(h, r));
+    if (h->timing) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, h->tev[0], h->tev[1]));
+      h->timed_ms += ms;
+      h->timed_launches += c->check_every;
+    }
     S_new = r[2];
     if (!std::isfinite(S_new)) {
       st = LBM_PT_NONFINITE;
@@ -350,7 +365,7 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
     return fail(LBM_ENOMEM);
   }
   for (int i = 0; i < 2; ++i)
-    if (hipEventCreate(&h->ev[i]) != hipSuccess) {
+    if (hipEventCreate(&h->ev[i]) != hipSuccess || hipEventCreate(&h->tev[i]) != hipSuccess) {
       set_err("hipEventCreate failed");
       return fail(LBM_EHIP);
     }
@@ -692,6 +707,21 @@ int lbm_time_steps(lbm_throat_t h, long long nsteps, double *ms) {
   return LBM_OK;
 }
 
+int lbm_step_timer(lbm_throat_t h, int enable, double *total_ms, long long *launches) {
+  if (!h) {
+    set_err("NULL handle");
+    return LBM_EINVAL;
+  }
+  if (total_ms) *total_ms = h->timed_ms;
+  if (launches) *launches = h->timed_launches;
+  if (enable >= 0) {
+    h->timing = enable != 0;
+    h->timed_ms = 0.0;
+    h->timed_launches = 0;
+  }
+  return LBM_OK;
+}
+
 int lbm_set_schedule(lbm_throat_t h, int tx, int ty, int lz) {
   if (!h) {
     set_err("NULL handle");
@@ -718,6 +748,47 @@ int lbm_get_schedule(lbm_throat_t h, int *tx, int *ty, int *lz) {
   if (ty) *ty = h->sched.ty;
   if (lz) *lz = h->sched.lz;
   return LBM_OK;
+}
+
+int lbm_bw_probe(size_t bytes, int reps, double *gbps) {
+  if (bytes < (1u << 20) || reps < 1 || !gbps) {
+    set_err("lbm_bw_probe: bytes >= 1 MiB, reps >= 1 and an output are required");
+    return LBM_EINVAL;
+  }
+  const size_t nf = bytes / 16 * 4;
+  float *a = nullptr, *b = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = LBM_OK;
+  if (hipMalloc((void **)&a, nf * sizeof(float)) != hipSuccess ||
+      hipMalloc((void **)&b, nf * sizeof(float)) != hipSuccess) {
+    set_err("lbm_bw_probe: hipMalloc of 2 x %zu bytes failed", nf * sizeof(float));
+    rc = LBM_ENOMEM;
+  }
+  if (rc == LBM_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+                       hipMemset(a, 0, nf * sizeof(float)) != hipSuccess)) {
+    set_err("lbm_bw_probe: setup failed");
+    rc = LBM_EHIP;
+  }
+  if (rc == LBM_OK) {
+    hipError_t e = sc::launch_copy(a, b, nf, nullptr);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+    for (int i = 0; i < reps && e == hipSuccess; ++i) e = sc::launch_copy(a, b, nf, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      set_err("lbm_bw_probe: %s", hipGetErrorString(e));
+      rc = LBM_EHIP;
+    } else {
+      *gbps = 2.0 * (double)nf * sizeof(float) * reps / (ms * 1e-3) / 1e9;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (a) (void)hipFree(a);
+  if (b) (void)hipFree(b);
+  return rc;
 }
 
 }  // extern "C"

@@ -57,6 +57,8 @@ hipError_t launch_density(const Dom &d, const Phys &P, const double *rres_d, dou
 hipError_t launch_reduce(const Dom &d, const Phys &P, double phib, long long probe,
                          double *partials, int n_partials, double *out, hipStream_t st);
 int reduce_blocks(size_t N);
+// plain copy of n_floats (a multiple of 4) floats, 16-byte aligned buffers
+hipError_t launch_copy(const float *a, float *b, size_t n_floats, hipStream_t st);
 
 bool schedule_valid(const Sched &s);
 

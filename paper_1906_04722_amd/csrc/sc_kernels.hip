@@ -65,19 +65,56 @@ __device__ __forceinline__ int wrap(int c, int n) { return c < 0 ? c + n : (c >=
 // Pull the pre-collision populations f(x,t) - w_k rho_ref of fluid node n at
 // (X, Y, Z): g_k from x - e_k, or the reflected g_opp(k) at x itself when the
 // link to x - e_k is cut by a solid node or a wall (half-way bounce-back).
-__device__ __forceinline__ void pull(const Dom &d, uint32_t m, size_t n, int X, int Y, int Z,
+// Addresses are a uniform plane base (scalar registers) plus a 32-bit byte
+// offset per lane: the pair of planes {k, opp(k)} is addressed from the lower
+// one, so offsets stay below 2 N * 4 bytes (N < 2^29 is enforced at init).
+template <int K>
+__device__ __forceinline__ void pull_dir(const Dom &d, uint32_t m, uint32_t n, uint32_t s,
+                                         float (&v)[2][19]) {
+  constexpr int o = opp(K);
+  constexpr int mn = K < o ? K : o;
+  const uint32_t N = (uint32_t)d.N;
+  const bool cut = (m >> K) & 1u;
+  const uint32_t off = cut ? (uint32_t)(o - mn) * N + n : (uint32_t)(K - mn) * N + s;
+  const char *b0 = (const char *)(d.src + (size_t)mn * d.N);
+  const char *b1 = (const char *)(d.src + (size_t)(19 + mn) * d.N);
+  v[0][K] = *(const float *)(b0 + (size_t)(off * 4u));
+  v[1][K] = *(const float *)(b1 + (size_t)(off * 4u));
+}
+
+template <int K>
+__device__ __forceinline__ uint32_t src_index(uint32_t n, uint32_t nx, uint32_t nxy, uint32_t cxm,
+                                              uint32_t cxp, uint32_t cym, uint32_t cyp,
+                                              uint32_t czm, uint32_t czp) {
+  // x - e_k in modular 32-bit arithmetic; the c?? terms wrap across a
+  // periodic face (on other faces the link is cut and the value is unused)
+  uint32_t s = n;
+  if (ex(K) > 0) s = s - 1u + cxm;
+  if (ex(K) < 0) s = s + 1u - cxp;
+  if (ey(K) > 0) s = s - nx + cym;
+  if (ey(K) < 0) s = s + nx - cyp;
+  if (ez(K) > 0) s = s - nxy + czm;
+  if (ez(K) < 0) s = s + nxy - czp;
+  return s;
+}
+
+template <int K>
+__device__ __forceinline__ void pull_rec(const Dom &d, uint32_t m, uint32_t n, uint32_t nx,
+                                         uint32_t nxy, uint32_t cxm, uint32_t cxp, uint32_t cym,
+                                         uint32_t cyp, uint32_t czm, uint32_t czp,
+                                         float (&v)[2][19]) {
+  pull_dir<K>(d, m, n, src_index<K>(n, nx, nxy, cxm, cxp, cym, cyp, czm, czp), v);
+  if constexpr (K + 1 < 19) pull_rec<K + 1>(d, m, n, nx, nxy, cxm, cxp, cym, cyp, czm, czp, v);
+}
+
+__device__ __forceinline__ void pull(const Dom &d, uint32_t m, uint32_t n, int X, int Y, int Z,
                                      float (&v)[2][19]) {
-#pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    const bool cut = (m >> k) & 1u;
-    const int sx = wrap(X - ex(k), d.nx);
-    const int sy = wrap(Y - ey(k), d.ny);
-    const int sz = wrap(Z - ez(k), d.nz);
-    const size_t s = (size_t)sx + (size_t)d.nx * ((size_t)sy + (size_t)d.ny * (size_t)sz);
-    const float *p = cut ? d.src + (size_t)opp(k) * d.N + n : d.src + (size_t)k * d.N + s;
-    v[0][k] = p[0];
-    v[1][k] = p[19 * d.N];
-  }
+  const uint32_t nx = (uint32_t)d.nx, nxy = (uint32_t)d.nx * (uint32_t)d.ny;
+  const uint32_t N = (uint32_t)d.N;
+  const uint32_t cxm = X == 0 ? nx : 0u, cxp = X == d.nx - 1 ? nx : 0u;
+  const uint32_t cym = Y == 0 ? nxy : 0u, cyp = Y == d.ny - 1 ? nxy : 0u;
+  const uint32_t czm = Z == 0 ? N : 0u, czp = Z == d.nz - 1 ? N : 0u;
+  pull_rec<0>(d, m, n, nx, nxy, cxm, cxp, cym, cyp, czm, czp, v);
 }
 
 // Arithmetic type of the update.  Populations are stored in FP32 (the HBM
@@ -115,11 +152,11 @@ __device__ __forceinline__ float2 density_at(const Dom &d, const Phys &P, int X,
   if (t == kResOut) return make_float2(P.rres[1][0], P.rres[1][1]);
   int X2 = wrap(X, d.nx), Y2 = wrap(Y, d.ny), Z2 = wrap(Z, d.nz);
   if (KEEP) {
-    pull(d, m, (size_t)n, X2, Y2, Z2, v);
+    pull(d, m, (uint32_t)n, X2, Y2, Z2, v);
     return make_float2((float)((acc_t)P.rho_ref + sum19(v[0])), (float)((acc_t)P.rho_ref + sum19(v[1])));
   } else {
     float t2[2][19];
-    pull(d, m, (size_t)n, X2, Y2, Z2, t2);
+    pull(d, m, (uint32_t)n, X2, Y2, Z2, t2);
     return make_float2((float)((acc_t)P.rho_ref + sum19(t2[0])), (float)((acc_t)P.rho_ref + sum19(t2[1])));
   }
 }
@@ -192,27 +229,52 @@ __device__ __forceinline__ void collide(const Phys &P, uint32_t m, const acc_t (
   }
 }
 
-__device__ __forceinline__ void store_node(const Dom &d, size_t n, const float (&v)[2][19]) {
+__device__ __forceinline__ void store_node(const Dom &d, uint32_t n, const float (&v)[2][19]) {
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int k = 0; k < 19; ++k)
-      __builtin_nontemporal_store(v[c][k], d.dst + (size_t)(c * 19 + k) * d.N + n);
+    for (int k = 0; k < 19; ++k) {
+      char *b = (char *)(d.dst + (size_t)(c * 19 + k) * d.N);
+      __builtin_nontemporal_store(v[c][k], (float *)(b + (size_t)(n * 4u)));
+    }
 }
 
 // ---- fused step ------------------------------------------------------------
 // A workgroup owns a TX x TY column of nodes and marches it through a
-// z-segment.  For each plane it pulls its own nodes (kept in registers for the
-// collision one plane later) and the one-node halo ring around the tile (for
-// densities only), writes both densities into a 4-plane LDS ring, and
-// collides the plane below with the 18-neighbour density stencil.
+// z-segment, software-pipelined over three planes.  Entering iteration Z, the
+// thread holds its own node of plane Z in registers, its node of plane Z+1 in
+// a private LDS slot, and the LDS density ring holds planes Z-1..Z+1.  It
+//   1. issues the pulls of plane Z+2 for its halo node and its own node,
+//   2. sums the halo pull into the ring (plane Z+2),
+//   3. collides plane Z with the 18-neighbour density stencil while the own
+//      pull is still in flight, and stores it,
+//   4. sums the own pull into the ring, rotates plane Z+1 from LDS into
+//      registers and parks plane Z+2 in LDS,
+//   5. synchronises the workgroup.
+// Every population is read from memory once per step (halo pulls re-read
+// neighbour tiles' lines, which are normally still in L2).
+template <int TX, int TY>
+__device__ __forceinline__ void halo_slot(int h, int &hx, int &hy) {
+  constexpr int HR = 2 * (TX + 2);
+  if (h < HR) {
+    hx = h % (TX + 2) - 1;
+    hy = h < TX + 2 ? -1 : TY;
+  } else {
+    const int u = h - HR;
+    hx = u < TY ? -1 : TX;
+    hy = u % TY;
+  }
+}
+
 template <int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void k_step(Dom d, Phys P, int lz, int ntx, int nty,
                                                  int nblocks) {
+  constexpr int NT = TX * TY;
+  constexpr int H = 2 * (TX + 2) + 2 * TY;  // halo ring of one plane
+  static_assert(NT >= H, "tile too small for its halo");
   __shared__ float2 ring[4][TY + 2][TX + 2];
-  constexpr int HR = 2 * (TX + 2);  // halo rows y0-1 and y0+TY, x in [-1, TX]
-  constexpr int H = HR + 2 * TY;    // plus halo columns x0-1 and x0+TX
-  static_assert(TX * TY >= H, "tile too small for its halo");
+  __shared__ float stage[38][NT];
+  __shared__ uint32_t stage_m[NT];
 
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
@@ -226,37 +288,38 @@ __global__ __launch_bounds__(TX *TY) void k_step(Dom d, Phys P, int lz, int ntx,
   const int z1 = min(z0 + lz, d.nz);
   const int x = x0 + tx, y = y0 + ty;
   const bool own = x < d.nx && y < d.ny;
-
   const bool halo = tid < H;
   int hx = 0, hy = 0;
-  if (tid < HR) {
-    hx = tid % (TX + 2) - 1;
-    hy = tid < TX + 2 ? -1 : TY;
-  } else if (halo) {
-    const int u = tid - HR;
-    hx = u < TY ? -1 : TX;
-    hy = u % TY;
-  }
+  if (halo) halo_slot<TX, TY>(tid, hx, hy);
 
-  float cur[2][19], nxt[2][19];
-  uint32_t mcur = 0, mnxt = 0, mtmp;
-  {
-    float tmp[2][19];
-    ring[(z0 - 1) & 3][ty + 1][tx + 1] = density_at<false>(d, P, x, y, z0 - 1, tmp, mtmp);
-    if (halo) ring[(z0 - 1) & 3][hy + 1][hx + 1] = density_at<false>(d, P, x0 + hx, y0 + hy, z0 - 1, tmp, mtmp);
-    ring[z0 & 3][ty + 1][tx + 1] = density_at<true>(d, P, x, y, z0, cur, mcur);
-    if (halo) ring[z0 & 3][hy + 1][hx + 1] = density_at<false>(d, P, x0 + hx, y0 + hy, z0, tmp, mtmp);
-  }
+  float cur[2][19], nxt[2][19], hv[2][19];
+  uint32_t mcur = 0, mnxt = 0, mh;
+
+  // prologue: densities of planes z0-1 .. z0+1, populations of z0 and z0+1
+  ring[(z0 - 1) & 3][ty + 1][tx + 1] = density_at<false>(d, P, x, y, z0 - 1, hv, mh);
+  if (halo) ring[(z0 - 1) & 3][hy + 1][hx + 1] = density_at<false>(d, P, x0 + hx, y0 + hy, z0 - 1, hv, mh);
+  ring[z0 & 3][ty + 1][tx + 1] = density_at<true>(d, P, x, y, z0, cur, mcur);
+  if (halo) ring[z0 & 3][hy + 1][hx + 1] = density_at<false>(d, P, x0 + hx, y0 + hy, z0, hv, mh);
+  ring[(z0 + 1) & 3][ty + 1][tx + 1] = density_at<true>(d, P, x, y, z0 + 1, nxt, mnxt);
+  if (halo) ring[(z0 + 1) & 3][hy + 1][hx + 1] = density_at<false>(d, P, x0 + hx, y0 + hy, z0 + 1, hv, mh);
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int k = 0; k < 19; ++k) stage[c * 19 + k][tid] = nxt[c][k];
+  stage_m[tid] = mnxt;
+  __syncthreads();
+
   for (int Z = z0; Z < z1; ++Z) {
-    {
-      float tmp[2][19];
-      ring[(Z + 1) & 3][ty + 1][tx + 1] = density_at<true>(d, P, x, y, Z + 1, nxt, mnxt);
-      if (halo) ring[(Z + 1) & 3][hy + 1][hx + 1] = density_at<false>(d, P, x0 + hx, y0 + hy, Z + 1, tmp, mtmp);
-    }
-    __syncthreads();
+    const bool ahead = Z + 2 <= z1;  // plane Z+2 is needed (density halo or next own)
+    // 1-2. halo node of plane Z+2, then own node of plane Z+2 (left in flight)
+    if (ahead && halo)
+      ring[(Z + 2) & 3][hy + 1][hx + 1] = density_at<false>(d, P, x0 + hx, y0 + hy, Z + 2, hv, mh);
+    float2 rho_ahead = make_float2(0.f, 0.f);
+    if (ahead) rho_ahead = density_at<true>(d, P, x, y, Z + 2, nxt, mnxt);
+    // 3. collide plane Z
     if (own) {
+      const uint32_t n = (uint32_t)x + (uint32_t)d.nx * ((uint32_t)y + (uint32_t)d.ny * (uint32_t)Z);
       const uint32_t t = mcur >> kTypeShift;
-      const size_t n = (size_t)x + (size_t)d.nx * ((size_t)y + (size_t)d.ny * (size_t)Z);
       if (t == kFluid) {
         acc_t Sw[3] = {0, 0, 0}, Sn[3] = {0, 0, 0};
 #pragma unroll
@@ -278,17 +341,25 @@ __global__ __launch_bounds__(TX *TY) void k_step(Dom d, Phys P, int lz, int ntx,
         store_node(d, n, cur);
       }
     }
+    // 4. publish plane Z+2, rotate Z+1 -> registers, Z+2 -> LDS
+    if (ahead) ring[(Z + 2) & 3][ty + 1][tx + 1] = rho_ahead;
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-      for (int k = 0; k < 19; ++k) cur[c][k] = nxt[c][k];
-    mcur = mnxt;
+      for (int k = 0; k < 19; ++k) {
+        cur[c][k] = stage[c * 19 + k][tid];
+        stage[c * 19 + k][tid] = nxt[c][k];
+      }
+    mcur = stage_m[tid];
+    stage_m[tid] = mnxt;
+    // 5.
+    __syncthreads();
   }
 }
 
 bool schedule_valid(const Sched &s) {
-  return (s.tx == 32 || s.tx == 64) && (s.ty == 4 || s.ty == 8 || s.ty == 16) && s.lz >= 1 &&
-         !(s.tx == 64 && s.ty == 16);
+  // (64, 8) and (32, 16) would need 2 x 78 KB of LDS staging: not offered
+  return ((s.tx == 32 && (s.ty == 4 || s.ty == 8)) || (s.tx == 64 && s.ty == 4)) && s.lz >= 1;
 }
 
 template <int TX, int TY>
@@ -305,11 +376,9 @@ hipError_t launch_step(const Dom &d, const Phys &P, const Sched &s, hipStream_t 
   if (!schedule_valid(s)) return hipErrorInvalidValue;
   if (s.tx == 32) {
     if (s.ty == 4) return step_as<32, 4>(d, P, s.lz, st);
-    if (s.ty == 8) return step_as<32, 8>(d, P, s.lz, st);
-    return step_as<32, 16>(d, P, s.lz, st);
+    return step_as<32, 8>(d, P, s.lz, st);
   }
-  if (s.ty == 4) return step_as<64, 4>(d, P, s.lz, st);
-  return step_as<64, 8>(d, P, s.lz, st);
+  return step_as<64, 4>(d, P, s.lz, st);
 }
 
 // ---- geometry ----------------------------------------------------------------
@@ -446,7 +515,7 @@ __global__ void k_export(Dom d, Phys P, const double *rres, double *f) {
     const uint32_t m = d.mask[n];
     const uint32_t t = m >> kTypeShift;
     float v[2][19];
-    if (t == kFluid) pull(d, m, n, x, y, z, v);
+    if (t == kFluid) pull(d, m, (uint32_t)n, x, y, z, v);
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -476,7 +545,7 @@ __global__ void k_density(Dom d, Phys P, const double *rres, double *rho) {
     double r0 = 0.0, r1 = 0.0;
     if (t == kFluid) {
       float v[2][19];
-      pull(d, m, n, x, y, z, v);
+      pull(d, m, (uint32_t)n, x, y, z, v);
       r0 = (double)(float)((acc_t)P.rho_ref + sum19(v[0]));
       r1 = (double)(float)((acc_t)P.rho_ref + sum19(v[1]));
     } else if (t == kResIn) {
@@ -538,7 +607,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(Dom d, Phys P, double ph
     if ((m >> kTypeShift) != kFluid) continue;
     const int x = (int)(n % d.nx), y = (int)((n / d.nx) % d.ny), z = (int)(n / ((size_t)d.nx * d.ny));
     float v[2][19];
-    pull(d, m, n, x, y, z, v);
+    pull(d, m, (uint32_t)n, x, y, z, v);
     const double a = (double)(float)((acc_t)P.rho_ref + sum19(v[0]));
     const double b = (double)(float)((acc_t)P.rho_ref + sum19(v[1]));
     acc[0] += a;
@@ -572,6 +641,25 @@ hipError_t launch_reduce(const Dom &d, const Phys &P, double phib, long long pro
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, st, partials, n_partials, out);
+  return hipGetLastError();
+}
+
+// ---- stream-copy probe: achievable HBM bandwidth on this device ----------
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// one 16-byte element per thread, plain loads and stores (the fastest copy
+// form measured on this device)
+__global__ __launch_bounds__(256) void k_copy(const v4f *__restrict__ a, v4f *__restrict__ b,
+                                              size_t n4) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i < n4) b[i] = a[i];
+}
+
+hipError_t launch_copy(const float *a, float *b, size_t n_floats, hipStream_t st) {
+  const size_t n4 = n_floats / 4;
+  const size_t blocks = (n4 + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const v4f *)a, (v4f *)b, n4);
   return hipGetLastError();
 }
 

@@ -74,6 +74,8 @@ SIGNATURES = {
     "lbm_time_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_longlong, _dp]),
     "lbm_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "lbm_get_schedule": (ctypes.c_int, [ctypes.c_void_p, _ip, _ip, _ip]),
+    "lbm_bw_probe": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, _dp]),
+    "lbm_step_timer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _llp]),
     "lbm_last_error": (ctypes.c_char_p, []),
 }
 
@@ -228,6 +230,15 @@ class Throat:
         _check(lib().lbm_time_steps(self.h, int(n), ctypes.byref(ms)), "lbm_time_steps")
         return ms.value
 
+    def step_timer(self, enable=-1):
+        """(ms, launches) of event-timed step launches inside drain(); enable
+        1/0 resets and switches timing, -1 only reads."""
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_longlong(0)
+        _check(lib().lbm_step_timer(self.h, int(enable), ctypes.byref(ms), ctypes.byref(n)),
+               "lbm_step_timer")
+        return ms.value, n.value
+
     def set_schedule(self, tx=0, ty=0, lz=0):
         _check(lib().lbm_set_schedule(self.h, int(tx), int(ty), int(lz)), "lbm_set_schedule")
 
@@ -236,6 +247,13 @@ class Throat:
         _check(lib().lbm_get_schedule(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
                "lbm_get_schedule")
         return a.value, b.value, c.value
+
+
+def bw_probe(nbytes=4 << 30, reps=20):
+    """Achievable copy bandwidth in GB/s (read + write)."""
+    v = ctypes.c_double(0.0)
+    _check(lib().lbm_bw_probe(int(nbytes), int(reps), ctypes.byref(v)), "lbm_bw_probe")
+    return v.value
 
 
 def nan_safe(x):

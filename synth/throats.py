@@ -87,3 +87,29 @@ def small_throat_problem(n=24, seed=7, amp=1e-3, rho_in=2.05, gap=2.0):
     p.rho_init = layered_density(n, n, n, p.z_front, p.rho_major, p.rho_minor, seed, amp)
     return p
 
+
+
+def throat_incircle(spheres, ids=(0, 1, 2)):
+    """Radius and centre of the circle in the xy-plane tangent to the three
+    throat circles (sphere cross-sections through their centres): the
+    inscribed opening used by the incircle estimate of the entry pressure."""
+    from scipy.optimize import fsolve
+    c = np.asarray(spheres, dtype=np.float64)[list(ids)]
+    P = c[:, :2]
+    R = c[:, 3]
+
+    def eqs(v):
+        return [np.hypot(v[0] - P[i, 0], v[1] - P[i, 1]) - (v[2] + R[i]) for i in range(3)]
+
+    cen = P.mean(axis=0)
+    r0 = np.mean(np.hypot(*(P - cen).T)) - R.mean()
+    sol = fsolve(eqs, [cen[0], cen[1], max(r0, 0.5)], full_output=True)
+    v = sol[0]
+    return float(v[2]), (float(v[0]), float(v[1]))
+
+
+def pc_ramp(gamma, r_ins, n, lo=0.1, hi=1.5):
+    """n equally spaced capillary pressures from lo to hi times the incircle
+    estimate 2 gamma / r_ins of a perfectly wetting throat."""
+    p_hat = 2.0 * gamma / r_ins
+    return np.linspace(lo, hi, n) * p_hat

@@ -100,7 +100,7 @@ def test_schedules_agree_bitwise():
     lbm = _lbm()
     p = _ragged_problem()
     ref = None
-    for tx, ty, lz in [(64, 8, 16), (32, 4, 3), (32, 16, 29), (64, 4, 1), (32, 8, 7)]:
+    for tx, ty, lz in [(64, 4, 16), (32, 4, 3), (32, 8, 29), (64, 4, 1), (32, 8, 7), (64, 4, 2)]:
         g = lbm.Throat(p)
         g.set_schedule(tx, ty, lz)
         g.step(30)
