@@ -1,0 +1,108 @@
+"""Profiling driver for rocprofv3 runs of the fused step, and the summary
+writer for the counter output.
+
+  python3 -m paper_1906_04722_amd.profile_run run --steps 200
+      builds the 96^3 throat, runs a 1 GiB copy twice (the counter calibration:
+      2 GiB moved per launch, known exactly) and `steps` fused steps.
+  python3 -m paper_1906_04722_amd.profile_run summarize --stats S.csv
+      --fetch F.csv --write W.csv --out profiles/NAME.txt --command "..."
+      writes the per-launch averages of the step kernel, the copy-kernel
+      calibration factors and the calibrated HBM traffic per launch.
+"""
+import argparse
+import csv
+import hashlib
+import os
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+COPY_BYTES = 1 << 30
+
+
+def cmd_run(a):
+    sys.path.insert(0, ROOT)
+    import synth
+    from paper_1906_04722_amd import lbm
+    lbm.bw_probe(COPY_BYTES, 2)
+    if a.workload == "c2":
+        p = synth.c2_problem()
+    else:
+        n = int(a.workload)
+        p = synth.Problem(nx=n, ny=n, nz=n, bc=(synth.BC_PERIODIC,) * 3, z_front=n // 2,
+                          G_ads=(0.0, 0.0))
+    g = lbm.Throat(p)
+    g.step(a.steps)
+    g.sync()
+    print(f"profile_run: {a.workload}, {a.steps} steps, schedule {g.schedule()}", flush=True)
+
+
+def _per_kernel(path, counter=None):
+    out = {}
+    for r in csv.DictReader(open(path)):
+        if counter and r.get("Counter_Name") != counter:
+            continue
+        name = r["Kernel_Name"]
+        out.setdefault(name, []).append(float(r["Counter_Value"]))
+    return out
+
+
+def cmd_summarize(a):
+    stats = list(csv.DictReader(open(a.stats)))
+    fetch = _per_kernel(a.fetch, "FETCH_SIZE")
+    write = _per_kernel(a.write, "WRITE_SIZE")
+
+    def find(d, key):
+        for k, v in d.items():
+            if key in k:
+                return v
+        raise KeyError(key)
+
+    cf = find(fetch, "k_copy")
+    cw = find(write, "k_copy")
+    # counters are KiB per dispatch; the copy moves COPY_BYTES each way
+    f_scale = COPY_BYTES / (sum(cf) / len(cf) * 1024.0)
+    w_scale = COPY_BYTES / (sum(cw) / len(cw) * 1024.0)
+    sf = find(fetch, "k_step")
+    sw = find(write, "k_step")
+    fb = sum(sf) / len(sf) * 1024.0 * f_scale
+    wb = sum(sw) / len(sw) * 1024.0 * w_scale
+    sha = hashlib.sha256(open(os.path.join(PKG, "csrc", "sc_kernels.hip"), "rb").read())
+    lines = [f"# {a.title}", f"# command: {a.command}",
+             f"kernel_sha: {sha.hexdigest()[:16]}",
+             f"copy_fetch_scale: {f_scale:.4f}", f"copy_write_scale: {w_scale:.4f}",
+             f"step_launches_counted: {len(sf)}",
+             f"fetch_bytes_per_launch: {fb:.0f}", f"write_bytes_per_launch: {wb:.0f}",
+             f"traffic_bytes_per_launch: {fb + wb:.0f}"]
+    if a.alg_bytes:
+        lines.append(f"algorithmic_bytes_per_launch: {a.alg_bytes}")
+        lines.append(f"traffic_over_algorithmic: {(fb + wb) / float(a.alg_bytes):.3f}")
+    lines.append("# kernel stats (rocprofv3 --kernel-trace --stats):")
+    lines.append("# name | calls | avg_ns | min_ns | max_ns | percent")
+    for r in stats:
+        lines.append(f"# {r['Name'][:70]} | {r['Calls']} | {float(r['AverageNs']):.0f} | "
+                     f"{r['MinNs']} | {r['MaxNs']} | {float(r['Percentage']):.2f}")
+    open(a.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    r = sub.add_parser("run")
+    r.add_argument("--steps", type=int, default=200)
+    r.add_argument("--workload", default="c2")
+    s = sub.add_parser("summarize")
+    s.add_argument("--stats", required=True)
+    s.add_argument("--fetch", required=True)
+    s.add_argument("--write", required=True)
+    s.add_argument("--out", required=True)
+    s.add_argument("--title", default="fused step")
+    s.add_argument("--command", default="")
+    s.add_argument("--alg-bytes", type=int, default=0)
+    a = ap.parse_args()
+    cmd_run(a) if a.cmd == "run" else cmd_summarize(a)
+
+
+if __name__ == "__main__":
+    main()
