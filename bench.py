@@ -28,7 +28,7 @@ from paper_1906_04722_amd import lbm  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, vendor figure
 BYTES_PER_FLUID_NODE = 304   # 2 components x 19 FP32 populations, read + write
-GAMMA = 0.196                # interfacial tension of the model at G = 0.9 (Laplace fit)
+GAMMA = synth.GAMMA_LAPLACE  # interfacial tension of the model (Laplace fit)
 N_PC = 20
 CONV = dict(tol=1e-6, check_every=100, max_steps=20000, bisect_rel=0.005)
 KERNEL_SRC = os.path.join(ROOT, "paper_1906_04722_amd", "csrc", "sc_kernels.hip")

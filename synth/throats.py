@@ -108,6 +108,12 @@ def throat_incircle(spheres, ids=(0, 1, 2)):
     return float(v[2]), (float(v[0]), float(v[1]))
 
 
+# interfacial tension of the model at G = 0.9, tau = 1, majority density 2
+# (lattice units), from the Laplace-law fit of static cylinders pinned in the
+# oracle tests; it only sets the scale of the capillary-pressure ramps
+GAMMA_LAPLACE = 0.190
+
+
 def pc_ramp(gamma, r_ins, n, lo=0.1, hi=1.5):
     """n equally spaced capillary pressures from lo to hi times the incircle
     estimate 2 gamma / r_ins of a perfectly wetting throat."""

@@ -18,7 +18,7 @@ CONV = dict(tol=1e-5, check_every=100, max_steps=6000, bisect_rel=0.02)
 def _small_c2():
     p = synth.c2_problem(n=40, mean_r=32.0 * 40 / 96)
     r_ins, _ = synth.throat_incircle(p.spheres)
-    return p, synth.pc_ramp(0.196, r_ins, 5, 0.1, 0.7)
+    return p, synth.pc_ramp(synth.GAMMA_LAPLACE, r_ins, 5, 0.1, 0.7)
 
 
 def test_drain_parity_small_throat():
@@ -41,7 +41,7 @@ def test_full_size_ramp_invariants():
     from paper_1906_04722_amd import lbm
     p = synth.c2_problem()
     r_ins, _ = synth.throat_incircle(p.spheres)
-    pcs = synth.pc_ramp(0.196, r_ins, 8, 0.1, 0.8)
+    pcs = synth.pc_ramp(synth.GAMMA_LAPLACE, r_ins, 8, 0.1, 0.8)
     g = lbm.Throat(p)
     out = g.drain(pcs, tol=1e-6, check_every=100, max_steps=8000, bisect_rel=0.01)
     S = out["S"]
