@@ -66,11 +66,13 @@ def c2_workload():
 
 def one_drain(p, pcs):
     g = lbm.Throat(p)
+    sched = g.autotune(20)
     g.step_timer(1)
     out = g.drain(pcs, **CONV)
     ms, launches = g.step_timer(-1)
     n_fluid = int((g.types() == lbm.LBM_NODE_FLUID).sum())
     g.close()
+    out["schedule"] = sched
     return out, ms, launches, n_fluid
 
 
@@ -165,6 +167,7 @@ def main():
                    "check_every": CONV["check_every"], "max_steps_per_point": CONV["max_steps"]},
         "fluid_MLUPS": round(n_fluid * total_steps / dt / 1e6, 1),
         "lattice_steps_per_drain": total_steps // a.steps,
+        "schedule_autotuned": list(out["schedule"]),
         "pce": lbm.nan_safe(out["pce"]),
         "pce_bracket": [out["pce_lo"], lbm.nan_safe(out["pce_hi"])],
         "drainage_curve": {"pc": [round(float(x), 6) for x in pcs],

@@ -196,6 +196,12 @@ int lbm_step_timer(lbm_throat_t h, int enable, double *total_ms, long long *laun
 /* Launch shape of the fused step: tile (tx, ty) in {(32, 4), (32, 8),
  * (64, 4)}, z-segment length lz (>= 1).  0 keeps the current value. */
 int lbm_set_schedule(lbm_throat_t h, int tx, int ty, int lz);
+
+/* Autotune the launch shape for this subdomain: time `trial_steps` fused
+ * steps for every tile shape and z-segment length (the trials leave the state
+ * unchanged), keep the fastest and return it (outputs may be NULL).
+ * Synchronous. */
+int lbm_autotune(lbm_throat_t h, int trial_steps, int *tx, int *ty, int *lz);
 int lbm_get_schedule(lbm_throat_t h, int *tx, int *ty, int *lz);
 
 /* Stream-copy probe of the achievable HBM bandwidth (the measured roofline

@@ -73,6 +73,12 @@ struct lbm_throat {
   sc::Phys P{};
   sc::Sched sched{64, 4, 16};
   long long steps_done = 0;
+  // device descriptor and tile list of the fused step
+  sc::Throat desc{};
+  sc::Throat *desc_d = nullptr;
+  sc::TileRef *tiles_d = nullptr;
+  int ntiles = 0;
+  size_t tiles_cap = 0;
   // event-timed step launches inside the drainage ramp
   hipEvent_t tev[2] = {nullptr, nullptr};
   bool timing = false;
@@ -101,6 +107,52 @@ void fill_phys(lbm_throat *h) {
       P.rres[i][c] = (float)rr[i][c];
       P.gres[i][c] = (float)(rr[i][c] - ref);
     }
+}
+
+// refresh the device descriptor (buffers, sizes, tile grid, parameters)
+int sync_desc(lbm_throat *h) {
+  sc::Throat &T = h->desc;
+  T.g[0] = h->g[0];
+  T.g[1] = h->g[1];
+  T.mask = h->mask;
+  T.N = (uint32_t)h->N;
+  T.nx = h->nx;
+  T.ny = h->ny;
+  T.nz = h->nz;
+  T.per = h->per;
+  T.ntx = (h->nx + h->sched.tx - 1) / h->sched.tx;
+  T.nty = (h->ny + h->sched.ty - 1) / h->sched.ty;
+  T.lz = h->sched.lz;
+  T.active = 1;
+  T.P = h->P;
+  HIPCHK(hipMemcpyAsync(h->desc_d, &h->desc, sizeof(sc::Throat), hipMemcpyHostToDevice,
+                        h->stream));
+  return LBM_OK;
+}
+
+// tiles of the current schedule that hold a non-solid node
+int rebuild_tiles(lbm_throat *h) {
+  std::vector<sc::TileRef> list;
+  sc::list_tiles(h->types.data(), h->nx, h->ny, h->nz, h->sched.tx, h->sched.ty, h->sched.lz, 0,
+                 list);
+  if (list.size() > h->tiles_cap) {
+    if (h->tiles_d) HIPCHK(hipStreamSynchronize(h->stream));
+    if (h->tiles_d) (void)hipFree(h->tiles_d);
+    h->tiles_d = nullptr;
+    h->tiles_cap = 0;
+    if (hipMalloc((void **)&h->tiles_d, sizeof(sc::TileRef) * std::max<size_t>(list.size(), 1)) !=
+        hipSuccess) {
+      set_err("hipMalloc of the tile list failed");
+      return LBM_ENOMEM;
+    }
+    h->tiles_cap = list.size();
+  }
+  h->ntiles = (int)list.size();
+  if (!list.empty())
+    HIPCHK(hipMemcpyAsync(h->tiles_d, list.data(), sizeof(sc::TileRef) * list.size(),
+                          hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return sync_desc(h);
 }
 
 int upload_rres(lbm_throat *h) {
@@ -202,6 +254,8 @@ void release(lbm_throat *h) {
   if (h->types_d) (void)hipFree(h->types_d);
   if (h->rres_d) (void)hipFree(h->rres_d);
   if (h->partials) (void)hipFree(h->partials);
+  if (h->desc_d) (void)hipFree(h->desc_d);
+  if (h->tiles_d) (void)hipFree(h->tiles_d);
   if (h->red_d) (void)hipFree(h->red_d);
   if (h->red_h) (void)hipHostFree(h->red_h);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -210,8 +264,8 @@ void release(lbm_throat *h) {
 
 int run_steps(lbm_throat *h, long long n) {
   for (long long i = 0; i < n; ++i) {
-    const sc::Dom d = dom(h, h->g[h->cur], h->g[1 - h->cur]);
-    hipError_t e = sc::launch_step(d, h->P, h->sched, h->stream);
+    hipError_t e = sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, h->sched.tx, h->sched.ty,
+                                   h->cur, h->stream);
     if (e != hipSuccess) {
       set_err("step launch failed: %s", hipGetErrorString(e));
       return LBM_EHIP;
@@ -237,6 +291,7 @@ int reduce_now(lbm_throat *h, double out[5]) {
 int set_rho_in(lbm_throat *h, double r) {
   h->rho_in = r;
   fill_phys(h);
+  TRY(sync_desc(h));
   return upload_rres(h);
 }
 
@@ -360,6 +415,7 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
   ALLOC(h->rres_d, 4 * sizeof(double));
   ALLOC(h->partials, sizeof(double) * 3 * h->n_partials);
   ALLOC(h->red_d, 5 * sizeof(double));
+  ALLOC(h->desc_d, sizeof(sc::Throat));
   if (hipHostMalloc((void **)&h->red_h, 5 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     set_err("hipHostMalloc failed");
     return fail(LBM_ENOMEM);
@@ -458,6 +514,7 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
     return fail(LBM_EHIP);
   }
   h->cur = 0;
+  if (rebuild_tiles(h) != LBM_OK) return fail(LBM_EHIP);
   *out = h;
   return LBM_OK;
 #undef ALLOC
@@ -736,6 +793,45 @@ int lbm_set_schedule(lbm_throat_t h, int tx, int ty, int lz) {
     return LBM_EINVAL;
   }
   h->sched = s;
+  return rebuild_tiles(h);
+}
+
+int lbm_autotune(lbm_throat_t h, int trial_steps, int *tx, int *ty, int *lz) {
+  if (!h || trial_steps < 1) {
+    set_err("lbm_autotune: bad handle or trial_steps < 1");
+    return LBM_EINVAL;
+  }
+  // candidate launch shapes; every trial reads g[cur] and writes g[1-cur]
+  // without flipping, so the state is untouched
+  static const int shapes[3][2] = {{32, 4}, {32, 8}, {64, 4}};
+  static const int lzs[7] = {1, 2, 4, 8, 16, 32, 64};
+  const sc::Sched keep = h->sched;
+  sc::Sched best = keep;
+  double best_ms = INFINITY;
+  for (const auto &sh : shapes)
+    for (int l : lzs) {
+      if (l > h->nz) continue;
+      h->sched = sc::Sched{sh[0], sh[1], l};
+      TRY(rebuild_tiles(h));
+      for (int w = 0; w < 2; ++w)
+        HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sh[0], sh[1], h->cur, h->stream));
+      HIPCHK(hipEventRecord(h->ev[0], h->stream));
+      for (int i = 0; i < trial_steps; ++i)
+        HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sh[0], sh[1], h->cur, h->stream));
+      HIPCHK(hipEventRecord(h->ev[1], h->stream));
+      HIPCHK(hipEventSynchronize(h->ev[1]));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = h->sched;
+      }
+    }
+  h->sched = best;
+  TRY(rebuild_tiles(h));
+  if (tx) *tx = best.tx;
+  if (ty) *ty = best.ty;
+  if (lz) *lz = best.lz;
   return LBM_OK;
 }
 

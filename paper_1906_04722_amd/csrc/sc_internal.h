@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace sc {
 
 // node classes, stored in bits 24..25 of the per-node mask word; bits 0..18
@@ -38,6 +40,26 @@ struct Sched {
   int tx, ty, lz;
 };
 
+// one subdomain as the fused step sees it: both population buffers, the
+// mask, the size, the tile grid of the launch schedule and the parameters
+// (a launch covers the tiles of one or many of these)
+struct Throat {
+  float *g[2];           // A/B buffers; the state is in g[parity]
+  const uint32_t *mask;
+  uint32_t N;
+  int nx, ny, nz, per;
+  int ntx, nty, lz;      // tile grid: tiles of TX x TY nodes and lz planes
+  int active;            // 0: the launch skips this subdomain
+  Phys P;
+};
+
+// one tile of work: subdomain index and packed tile coordinate
+// tix + ntx * (tiy + nty * tiz)
+struct TileRef {
+  int throat;
+  int tile;
+};
+
 // kernel launchers (all asynchronous on `st`)
 hipError_t launch_voxelize(const double *spheres, int n_spheres, int prism, const int *prism_ids,
                            int nx, int ny, int nz, int bc_z_reservoir, uint8_t *types,
@@ -47,7 +69,14 @@ hipError_t launch_links(const uint8_t *types, int nx, int ny, int nz, int per, u
 hipError_t launch_init(const Dom &d, const Phys &P, const double *rho_init, double rho_major,
                        double rho_minor, int z_front, const double *rres_d, float *g,
                        hipStream_t st);
-hipError_t launch_step(const Dom &d, const Phys &P, const Sched &s, hipStream_t st);
+// one time step of every active subdomain in `throats` over the listed tiles
+// (device arrays); tx, ty is the tile shape the lists were built for
+hipError_t launch_step(const Throat *throats, const TileRef *tiles, int ntiles, int tx, int ty,
+                       int parity, hipStream_t st);
+// host: append the tiles of subdomain `throat` that hold at least one
+// non-solid node (solid-only tiles need no update)
+void list_tiles(const uint8_t *types, int nx, int ny, int nz, int tx, int ty, int lz, int throat,
+                std::vector<TileRef> &out);
 hipError_t launch_export(const Dom &d, const Phys &P, const double *rres_d, double *f,
                          hipStream_t st);
 hipError_t launch_density(const Dom &d, const Phys &P, const double *rres_d, double *rho,

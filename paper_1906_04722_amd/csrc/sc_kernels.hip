@@ -267,8 +267,9 @@ __device__ __forceinline__ void halo_slot(int h, int &hx, int &hy) {
 }
 
 template <int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void k_step(Dom d, Phys P, int lz, int ntx, int nty,
-                                                 int nblocks) {
+__global__ __launch_bounds__(TX *TY) void k_step(const Throat *__restrict__ throats,
+                                                 const TileRef *__restrict__ tiles, int ntiles,
+                                                 int parity) {
   constexpr int NT = TX * TY;
   constexpr int H = 2 * (TX + 2) + 2 * TY;  // halo ring of one plane
   static_assert(NT >= H, "tile too small for its halo");
@@ -278,12 +279,25 @@ __global__ __launch_bounds__(TX *TY) void k_step(Dom d, Phys P, int lz, int ntx,
 
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
-  // tiles are handed out so that each XCD (blocks b = xcd mod 8) gets one
-  // contiguous range of tiles, keeping spatial neighbours in one L2
+  // list entries are handed out so that each XCD (blocks b = xcd mod 8) gets
+  // one contiguous range of the tile list, keeping spatial neighbours in one L2
   const int b = blockIdx.x;
-  const int q = nblocks >> 3, r = nblocks & 7, xcd = b & 7, idx = b >> 3;
-  const int tile = xcd * q + min(xcd, r) + idx;
-  const int tix = tile % ntx, tiy = (tile / ntx) % nty, tiz = tile / (ntx * nty);
+  const int q = ntiles >> 3, r = ntiles & 7, xcd = b & 7, idx = b >> 3;
+  const TileRef tr = tiles[xcd * q + min(xcd, r) + idx];
+  const Throat &T = throats[tr.throat];
+  if (!T.active) return;
+  Dom d;
+  d.src = T.g[parity];
+  d.dst = T.g[parity ^ 1];
+  d.mask = T.mask;
+  d.N = T.N;
+  d.nx = T.nx;
+  d.ny = T.ny;
+  d.nz = T.nz;
+  d.per = T.per;
+  const Phys P = T.P;
+  const int ntx = T.ntx, nty = T.nty, lz = T.lz;
+  const int tix = tr.tile % ntx, tiy = (tr.tile / ntx) % nty, tiz = tr.tile / (ntx * nty);
   const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * lz;
   const int z1 = min(z0 + lz, d.nz);
   const int x = x0 + tx, y = y0 + ty;
@@ -363,22 +377,44 @@ bool schedule_valid(const Sched &s) {
 }
 
 template <int TX, int TY>
-static hipError_t step_as(const Dom &d, const Phys &P, int lz, hipStream_t st) {
-  const int ntx = (d.nx + TX - 1) / TX, nty = (d.ny + TY - 1) / TY, ntz = (d.nz + lz - 1) / lz;
-  const long long nb = (long long)ntx * nty * ntz;
-  if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_step<TX, TY>), dim3((unsigned)nb), dim3(TX * TY), 0, st, d, P, lz, ntx, nty,
-                     (int)nb);
+static hipError_t step_as(const Throat *th, const TileRef *tiles, int ntiles, int parity,
+                          hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_step<TX, TY>), dim3((unsigned)ntiles), dim3(TX * TY), 0, st, th, tiles,
+                     ntiles, parity);
   return hipGetLastError();
 }
 
-hipError_t launch_step(const Dom &d, const Phys &P, const Sched &s, hipStream_t st) {
-  if (!schedule_valid(s)) return hipErrorInvalidValue;
-  if (s.tx == 32) {
-    if (s.ty == 4) return step_as<32, 4>(d, P, s.lz, st);
-    return step_as<32, 8>(d, P, s.lz, st);
+hipError_t launch_step(const Throat *th, const TileRef *tiles, int ntiles, int tx, int ty,
+                       int parity, hipStream_t st) {
+  if (!schedule_valid(Sched{tx, ty, 1})) return hipErrorInvalidValue;
+  if (tx == 32) {
+    if (ty == 4) return step_as<32, 4>(th, tiles, ntiles, parity, st);
+    return step_as<32, 8>(th, tiles, ntiles, parity, st);
   }
-  return step_as<64, 4>(d, P, s.lz, st);
+  return step_as<64, 4>(th, tiles, ntiles, parity, st);
+}
+
+void list_tiles(const uint8_t *types, int nx, int ny, int nz, int tx, int ty, int lz, int throat,
+                std::vector<TileRef> &out) {
+  const int ntx = (nx + tx - 1) / tx, nty = (ny + ty - 1) / ty, ntz = (nz + lz - 1) / lz;
+  // liveness of each (x-tile, y-tile) cell of every plane, then of every z-segment
+  std::vector<uint8_t> cell((size_t)ntx * nty * nz, 0);
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y) {
+      const uint8_t *row = types + (size_t)nx * ((size_t)y + (size_t)ny * z);
+      uint8_t *c = cell.data() + (size_t)ntx * ((size_t)(y / ty) + (size_t)nty * z);
+      for (int x = 0; x < nx; ++x)
+        if (row[x] != kSolid) c[x / tx] = 1;
+    }
+  for (int tz = 0; tz < ntz; ++tz)
+    for (int tyi = 0; tyi < nty; ++tyi)
+      for (int txi = 0; txi < ntx; ++txi) {
+        bool live = false;
+        for (int z = tz * lz; z < std::min(nz, (tz + 1) * lz) && !live; ++z)
+          live = cell[(size_t)txi + (size_t)ntx * ((size_t)tyi + (size_t)nty * z)] != 0;
+        if (live) out.push_back(TileRef{throat, txi + ntx * (tyi + nty * tz)});
+      }
 }
 
 // ---- geometry ----------------------------------------------------------------

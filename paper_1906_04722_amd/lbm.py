@@ -74,6 +74,7 @@ SIGNATURES = {
     "lbm_time_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_longlong, _dp]),
     "lbm_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "lbm_get_schedule": (ctypes.c_int, [ctypes.c_void_p, _ip, _ip, _ip]),
+    "lbm_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _ip, _ip, _ip]),
     "lbm_bw_probe": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, _dp]),
     "lbm_step_timer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _llp]),
     "lbm_last_error": (ctypes.c_char_p, []),
@@ -241,6 +242,13 @@ class Throat:
 
     def set_schedule(self, tx=0, ty=0, lz=0):
         _check(lib().lbm_set_schedule(self.h, int(tx), int(ty), int(lz)), "lbm_set_schedule")
+
+    def autotune(self, trial_steps=20):
+        """Pick the fastest launch shape for this subdomain (state unchanged)."""
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().lbm_autotune(self.h, int(trial_steps), ctypes.byref(a), ctypes.byref(b),
+                                  ctypes.byref(c)), "lbm_autotune")
+        return a.value, b.value, c.value
 
     def schedule(self):
         a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

@@ -155,3 +155,20 @@ def test_closed_box_mass_drift_fp32():
     drift = np.abs(m1 - m0) / m0
     print("FP32 relative mass drift over 1000 steps", drift)
     assert drift.max() < 1e-5
+
+
+def test_autotune_keeps_state_and_results():
+    """The autotuner's trial launches leave the state untouched, and the
+    schedule it picks gives bit-identical results."""
+    lbm = _lbm()
+    p = _ragged_problem()
+    a = lbm.Throat(p)
+    a.step(10)
+    f0 = a.f()
+    sched = a.autotune(5)
+    assert np.array_equal(a.f(), f0)
+    a.step(20)
+    b = lbm.Throat(p)
+    b.step(30)
+    print("autotuned schedule", sched)
+    assert np.array_equal(a.f(), b.f())
