@@ -55,6 +55,7 @@ extern "C" {
 #define LBM_ENONFINITE (-4) /* the state became non-finite                  */
 #define LBM_ESTATE (-5)     /* call not valid in the handle's state         */
 #define LBM_WNOTCONV 1      /* a ramp point hit its step cap                */
+#define LBM_WPARTIAL 2      /* batch: some subdomains failed (see status)  */
 
 /* boundary kinds, one per axis */
 #define LBM_BC_PERIODIC 0
@@ -181,6 +182,32 @@ int lbm_probe_invaded(lbm_throat_t h, int *invaded);
  * hit its cap. */
 int lbm_drain_throat(lbm_throat_t h, const double *pc, int n_pc, const lbm_conv *c,
                      lbm_drain_result *out);
+
+/* Summary of a batched drainage (optional output of lbm_drain_batch). */
+typedef struct {
+  int tx, ty, lz;           /* launch shape chosen by the autotuner          */
+  int n_tiles;              /* live tiles of all subdomains in one launch    */
+  long long replays;        /* graph replays (chunks of check_every steps)   */
+  long long lattice_steps;  /* fused-step launches issued                    */
+  long long node_updates;   /* sum over subdomains of active steps x nodes   */
+  double wall_ms;           /* device time from the first to the last kernel */
+} lbm_batch_info;
+
+/* Batched drainage of n subdomains (Sec. 2.2.2: the throats are solved
+ * independently): p[t] states subdomain t (each needs a probe node), pc is
+ * host [n][n_pc] (each row strictly increasing), out[t] receives the same
+ * results as lbm_drain_throat would (bit for bit: the same kernels and the
+ * same reduction order).  One fused-step launch covers the live tiles of all
+ * running subdomains; the ramp and bisection decisions are taken on the
+ * device between chunks of c->check_every steps (even), captured once as a
+ * HIP graph and replayed until every subdomain is done.  The launch shape is
+ * autotuned over the whole batch.  Device memory: 4 x 152 bytes per node
+ * (two buffers and two ramp checkpoints) plus masks.  Synchronous.  Returns
+ * LBM_WNOTCONV if a point hit its cap, LBM_WPARTIAL if a subdomain became
+ * non-finite (its points carry LBM_PT_NONFINITE; the others are complete).
+ * info may be NULL. */
+int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, const lbm_conv *c,
+                    lbm_drain_result *out, lbm_batch_info *info);
 
 /* Time nsteps steps of the fused update with HIP events on the handle's
  * stream; *ms receives the elapsed milliseconds.  Synchronous. */

@@ -13,12 +13,14 @@
 #include <string>
 #include <vector>
 
+#include "lbm_handle.h"
 #include "sc_internal.h"
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
+namespace lbmh {
 void set_err(const char *fmt, ...) {
   char buf[512];
   va_list ap;
@@ -27,6 +29,10 @@ void set_err(const char *fmt, ...) {
   va_end(ap);
   g_err = buf;
 }
+}  // namespace lbmh
+
+namespace {
+using lbmh::set_err;
 
 #define HIPCHK(call)                                                          \
   do {                                                                        \
@@ -48,43 +54,6 @@ constexpr double kCs2 = 1.0 / 3.0;
 bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
 
 }  // namespace
-
-struct lbm_throat {
-  int nx = 0, ny = 0, nz = 0, per = 0, bc[3] = {0, 0, 0};
-  size_t N = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  float *g[2] = {nullptr, nullptr};  // A/B population buffers
-  int cur = 0;                       // g[cur] holds the current state
-  float *save[2] = {nullptr, nullptr};  // checkpoints used by the ramp
-  uint32_t *mask = nullptr;
-  uint8_t *types_d = nullptr;
-  double *rres_d = nullptr;          // [in/out][component]
-  double *partials = nullptr;
-  int n_partials = 0;
-  double *red_d = nullptr;           // [5]
-  double *red_h = nullptr;           // pinned [5]
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  std::vector<uint8_t> types;
-  long long n_fluid = 0;
-  long long probe = -1;
-  double tau[2], G, Gads[2], rho_major, rho_minor, rho_in, rho_out;
-  double phib = 1.0;
-  sc::Phys P{};
-  sc::Sched sched{64, 4, 16};
-  long long steps_done = 0;
-  // device descriptor and tile list of the fused step
-  sc::Throat desc{};
-  sc::Throat *desc_d = nullptr;
-  sc::TileRef *tiles_d = nullptr;
-  int ntiles = 0;
-  size_t tiles_cap = 0;
-  // event-timed step launches inside the drainage ramp
-  hipEvent_t tev[2] = {nullptr, nullptr};
-  bool timing = false;
-  double timed_ms = 0.0;
-  long long timed_launches = 0;
-};
 
 namespace {
 
@@ -254,6 +223,10 @@ void release(lbm_throat *h) {
   if (h->types_d) (void)hipFree(h->types_d);
   if (h->rres_d) (void)hipFree(h->rres_d);
   if (h->partials) (void)hipFree(h->partials);
+  if (h->chunks_d) (void)hipFree(h->chunks_d);
+  if (h->redinfo_d) (void)hipFree(h->redinfo_d);
+  if (h->chunk_first_d) (void)hipFree(h->chunk_first_d);
+  if (h->chunk_count_d) (void)hipFree(h->chunk_count_d);
   if (h->desc_d) (void)hipFree(h->desc_d);
   if (h->tiles_d) (void)hipFree(h->tiles_d);
   if (h->red_d) (void)hipFree(h->red_d);
@@ -276,11 +249,13 @@ int run_steps(lbm_throat *h, long long n) {
   return LBM_OK;
 }
 
-// FP64 masses, saturation and probe densities of the current state
+// FP64 masses, saturation and probe densities of the current state (the
+// chunked reduction the batched ramp uses too, so both give the same bits)
 int reduce_now(lbm_throat *h, double out[5]) {
-  const sc::Dom d = dom(h, h->g[h->cur], nullptr);
-  HIPCHK(sc::launch_reduce(d, h->P, h->phib, h->probe, h->partials, h->n_partials, h->red_d,
-                           h->stream));
+  HIPCHK(sc::launch_reduce_chunks(h->desc_d, h->chunks_d, h->nchunks, h->redinfo_d, h->cur,
+                                  h->partials, h->red_d + 3, h->stream));
+  HIPCHK(sc::launch_reduce_throats(h->chunk_first_d, h->chunk_count_d, 1, h->partials, h->red_d,
+                                   h->stream));
   HIPCHK(hipMemcpyAsync(h->red_h, h->red_d, 5 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   for (int i = 0; i < 5; ++i) out[i] = h->red_h[i];
@@ -339,6 +314,14 @@ int run_to_steady(lbm_throat *h, const lbm_conv *c, double *S_end, long long *us
 }
 
 }  // namespace
+
+namespace lbmh {
+int sync_desc(lbm_throat *h) { return ::sync_desc(h); }
+int rebuild_tiles(lbm_throat *h) { return ::rebuild_tiles(h); }
+int set_rho_in(lbm_throat *h, double r) { return ::set_rho_in(h, r); }
+int copy_state(lbm_throat *h, float *dst, const float *src) { return ::copy_state(h, dst, src); }
+}  // namespace lbmh
+
 
 extern "C" {
 
@@ -400,7 +383,6 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
     }
     h->own_stream = true;
   }
-  h->n_partials = sc::reduce_blocks(h->N);
 #define ALLOC(ptr, bytes)                                                      \
   do {                                                                         \
     if (hipMalloc((void **)&(ptr), (bytes)) != hipSuccess) {                   \
@@ -413,7 +395,24 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
   ALLOC(h->mask, sizeof(uint32_t) * h->N);
   ALLOC(h->types_d, h->N);
   ALLOC(h->rres_d, 4 * sizeof(double));
-  ALLOC(h->partials, sizeof(double) * 3 * h->n_partials);
+  {
+    std::vector<sc::Chunk> ch;
+    sc::list_chunks(0, (uint32_t)h->N, ch);
+    h->nchunks = (int)ch.size();
+    ALLOC(h->chunks_d, sizeof(sc::Chunk) * ch.size());
+    ALLOC(h->partials, sizeof(double) * 3 * ch.size());
+    ALLOC(h->chunk_first_d, sizeof(int));
+    ALLOC(h->chunk_count_d, sizeof(int));
+    ALLOC(h->redinfo_d, sizeof(sc::RedInfo));
+    const int first = 0, cnt = h->nchunks;
+    if (hipMemcpy(h->chunks_d, ch.data(), sizeof(sc::Chunk) * ch.size(), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(h->chunk_first_d, &first, sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->chunk_count_d, &cnt, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+      set_err("upload of the reduction chunks failed");
+      return fail(LBM_EHIP);
+    }
+  }
   ALLOC(h->red_d, 5 * sizeof(double));
   ALLOC(h->desc_d, sizeof(sc::Throat));
   if (hipHostMalloc((void **)&h->red_h, 5 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -482,6 +481,13 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
     if (h->types[h->probe] != sc::kFluid) {
       set_err("probe node is not a fluid node");
       return fail(LBM_EINVAL);
+    }
+  }
+  {
+    const sc::RedInfo ri{h->probe, h->phib};
+    if (hipMemcpy(h->redinfo_d, &ri, sizeof ri, hipMemcpyHostToDevice) != hipSuccess) {
+      set_err("upload of the reduction info failed");
+      return fail(LBM_EHIP);
     }
   }
   if (p->rho_init) {

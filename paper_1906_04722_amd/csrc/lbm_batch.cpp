@@ -1,0 +1,339 @@
+// lbm_batch.cpp -- batched drainage of many pore-throat subdomains
+// (Montella et al., Sec. 2.2.2: the pore throats are solved independently).
+//
+// Every subdomain keeps its own buffers and node classes; one fused-step
+// launch covers the live tiles of all active subdomains, and the ramp /
+// bisection decisions of every subdomain are taken on the device between
+// chunks of `check_every` steps.  The chunk [steps, reduction, decisions,
+// state copies] is captured once as a HIP graph and replayed until no
+// subdomain is running; the host only reads one counter between replays.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "lbm_abi.h"
+#include "lbm_handle.h"
+#include "sc_internal.h"
+
+using lbmh::set_err;
+
+namespace {
+
+constexpr double kCs2 = 1.0 / 3.0;
+
+struct Batch {
+  int n = 0;
+  hipStream_t stream = nullptr;
+  std::vector<lbm_throat_t> h;
+  sc::Throat *th_d = nullptr;
+  sc::TileRef *tiles_d = nullptr;
+  int ntiles = 0;
+  sc::Chunk *chunks_d = nullptr;
+  int nchunks = 0;
+  int *first_d = nullptr, *count_d = nullptr;
+  sc::RedInfo *info_d = nullptr;
+  double *partials = nullptr, *sums = nullptr, *probe = nullptr;
+  sc::RampDev *rd_d = nullptr;
+  sc::Ckpt *ck_d = nullptr;
+  double *pc_d = nullptr, *S_d = nullptr;
+  long long *steps_d = nullptr;
+  int *status_d = nullptr, *nact_d = nullptr, *nact_h = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::vector<sc::Throat> th_h;
+  sc::Sched sched{32, 4, 2};
+
+  ~Batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (void *p : {(void *)th_d, (void *)tiles_d, (void *)chunks_d, (void *)first_d,
+                    (void *)count_d, (void *)info_d, (void *)partials, (void *)sums,
+                    (void *)probe, (void *)rd_d, (void *)ck_d, (void *)pc_d, (void *)S_d,
+                    (void *)steps_d, (void *)status_d, (void *)nact_d})
+      if (p) (void)hipFree(p);
+    if (nact_h) (void)hipHostFree(nact_h);
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto x : h) lbm_throat_free(x);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+#define BCHK(call)                                                             \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      set_err("%s failed: %s", #call, hipGetErrorString(e_));                  \
+      return LBM_EHIP;                                                         \
+    }                                                                          \
+  } while (0)
+
+template <class T>
+int dalloc(T **p, size_t count) {
+  if (hipMalloc((void **)p, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess) {
+    set_err("hipMalloc of %zu bytes failed", sizeof(T) * count);
+    return LBM_ENOMEM;
+  }
+  return LBM_OK;
+}
+
+// tile lists of every subdomain for one launch shape
+int build_tiles(Batch &B, const sc::Sched &s) {
+  std::vector<sc::TileRef> tl;
+  for (int t = 0; t < B.n; ++t) {
+    const lbm_throat *x = B.h[t];
+    sc::list_tiles(x->types.data(), x->nx, x->ny, x->nz, s.tx, s.ty, s.lz, t, tl);
+    B.th_h[t].ntx = (x->nx + s.tx - 1) / s.tx;
+    B.th_h[t].nty = (x->ny + s.ty - 1) / s.ty;
+    B.th_h[t].lz = s.lz;
+  }
+  BCHK(hipStreamSynchronize(B.stream));
+  if (B.tiles_d) (void)hipFree(B.tiles_d);
+  B.tiles_d = nullptr;
+  if (dalloc(&B.tiles_d, tl.size())) return LBM_ENOMEM;
+  B.ntiles = (int)tl.size();
+  BCHK(hipMemcpy(B.tiles_d, tl.data(), sizeof(sc::TileRef) * tl.size(), hipMemcpyHostToDevice));
+  BCHK(hipMemcpy(B.th_d, B.th_h.data(), sizeof(sc::Throat) * B.n, hipMemcpyHostToDevice));
+  B.sched = s;
+  return LBM_OK;
+}
+
+// time candidate launch shapes over the whole batch (fixed parity: the
+// trials never change the state) and keep the fastest
+int autotune(Batch &B, int trial_steps) {
+  static const int shapes[3][2] = {{32, 4}, {32, 8}, {64, 4}};
+  static const int lzs[5] = {1, 2, 4, 8, 16};
+  sc::Sched best = B.sched;
+  double best_ms = INFINITY;
+  for (const auto &sh : shapes)
+    for (int l : lzs) {
+      const sc::Sched s{sh[0], sh[1], l};
+      if (int r = build_tiles(B, s)) return r;
+      for (int w = 0; w < 2; ++w)
+        BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream));
+      BCHK(hipEventRecord(B.ev[0], B.stream));
+      for (int i = 0; i < trial_steps; ++i)
+        BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream));
+      BCHK(hipEventRecord(B.ev[1], B.stream));
+      BCHK(hipEventSynchronize(B.ev[1]));
+      float ms = 0.f;
+      BCHK(hipEventElapsedTime(&ms, B.ev[0], B.ev[1]));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = s;
+      }
+    }
+  return build_tiles(B, best);
+}
+
+int capture_chunk(Batch &B, const sc::RampCfg &cfg) {
+  BCHK(hipStreamBeginCapture(B.stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < cfg.every && e == hipSuccess; ++i)
+    e = sc::launch_step(B.th_d, B.tiles_d, B.ntiles, B.sched.tx, B.sched.ty, i & 1, B.stream);
+  if (e == hipSuccess)
+    e = sc::launch_reduce_chunks(B.th_d, B.chunks_d, B.nchunks, B.info_d, 0, B.partials, B.probe,
+                                 B.stream);
+  if (e == hipSuccess)
+    e = sc::launch_reduce_throats(B.first_d, B.count_d, B.n, B.partials, B.sums, B.stream);
+  if (e == hipSuccess)
+    e = sc::launch_ramp_advance(B.th_d, B.rd_d, B.pc_d, cfg, B.sums, B.probe, B.S_d, B.steps_d,
+                                B.status_d, B.n, B.nact_d, B.stream);
+  if (e == hipSuccess)
+    e = sc::launch_copy_requests(B.th_d, B.rd_d, B.ck_d, B.chunks_d, B.nchunks, 0, B.stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(B.stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    set_err("graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    return LBM_EHIP;
+  }
+  B.graph = g;
+  BCHK(hipGraphInstantiate(&B.exec, g, nullptr, nullptr, 0));
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, const lbm_conv *c,
+                    lbm_drain_result *out, lbm_batch_info *info) {
+  if (n < 1 || !p || !pc || n_pc < 1 || !c || !out) {
+    set_err("lbm_drain_batch: n >= 1, params, pc, conv and results are required");
+    return LBM_EINVAL;
+  }
+  if (!(c->tol > 0) || c->check_every < 2 || (c->check_every & 1) ||
+      c->max_steps < c->check_every || !(c->bisect_rel > 0)) {
+    set_err("lbm_drain_batch: tol > 0, an even check_every >= 2, max_steps >= check_every and "
+            "bisect_rel > 0 are required");
+    return LBM_EINVAL;
+  }
+  for (int t = 0; t < n; ++t) {
+    if (!out[t].S || !out[t].steps || !out[t].status) {
+      set_err("lbm_drain_batch: result %d has no output arrays", t);
+      return LBM_EINVAL;
+    }
+    if (p[t].probe[0] < 0) {
+      set_err("lbm_drain_batch: subdomain %d has no probe node", t);
+      return LBM_EINVAL;
+    }
+    for (int i = 0; i < n_pc; ++i) {
+      const double v = pc[(size_t)t * n_pc + i];
+      if (!std::isfinite(v) || (i > 0 && !(v > pc[(size_t)t * n_pc + i - 1])) ||
+          !(p[t].rho_out_w + v / (kCs2 * (1.0 + p[t].G * p[t].rho_minor)) > 0)) {
+        set_err("lbm_drain_batch: pc of subdomain %d must be finite, strictly increasing and "
+                "give a positive inlet density", t);
+        return LBM_EINVAL;
+      }
+    }
+  }
+  Batch B;
+  B.n = n;
+  BCHK(hipStreamCreate(&B.stream));
+  BCHK(hipEventCreate(&B.ev[0]));
+  BCHK(hipEventCreate(&B.ev[1]));
+  // subdomains: geometry, initial state, checkpoints
+  std::vector<sc::Chunk> chunks;
+  std::vector<int> first(n), count(n);
+  std::vector<sc::RedInfo> rinfo(n);
+  std::vector<sc::RampDev> rd(n);
+  std::vector<sc::Ckpt> ck(n);
+  B.th_h.resize(n);
+  for (int t = 0; t < n; ++t) {
+    lbm_params q = p[t];
+    q.stream = B.stream;
+    lbm_throat_t x = nullptr;
+    if (int r = lbm_throat_init(&q, &x)) {
+      if (r < 0) return r;
+    }
+    B.h.push_back(x);
+    for (int i = 0; i < 2; ++i)
+      if (!x->save[i] && hipMalloc((void **)&x->save[i], sizeof(float) * 38 * x->N) != hipSuccess) {
+        set_err("lbm_drain_batch: no device memory for the checkpoints of subdomain %d", t);
+        return LBM_ENOMEM;
+      }
+    B.th_h[t] = x->desc;
+    ck[t] = sc::Ckpt{x->save[0], x->save[1]};
+    first[t] = (int)chunks.size();
+    sc::list_chunks(t, (uint32_t)x->N, chunks);
+    count[t] = (int)chunks.size() - first[t];
+    rinfo[t] = sc::RedInfo{x->probe, x->phib};
+    sc::RampDev R{};
+    R.rho_out = x->rho_out;
+    R.dpc_drho = kCs2 * (1.0 + x->G * x->rho_minor);
+    R.rho_ref = x->rho_minor;
+    R.n_fluid = (unsigned)x->n_fluid;
+    R.phase = sc::kPhaseDone;
+    rd[t] = R;
+  }
+  B.nchunks = (int)chunks.size();
+  if (dalloc(&B.th_d, n) || dalloc(&B.chunks_d, chunks.size()) || dalloc(&B.first_d, n) ||
+      dalloc(&B.count_d, n) || dalloc(&B.info_d, n) || dalloc(&B.partials, 3 * chunks.size()) ||
+      dalloc(&B.sums, 3 * (size_t)n) || dalloc(&B.probe, 2 * (size_t)n) || dalloc(&B.rd_d, n) ||
+      dalloc(&B.ck_d, n) || dalloc(&B.pc_d, (size_t)n * n_pc) || dalloc(&B.S_d, (size_t)n * n_pc) ||
+      dalloc(&B.steps_d, (size_t)n * n_pc) || dalloc(&B.status_d, (size_t)n * n_pc) ||
+      dalloc(&B.nact_d, 1))
+    return LBM_ENOMEM;
+  if (hipHostMalloc((void **)&B.nact_h, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    set_err("hipHostMalloc failed");
+    return LBM_ENOMEM;
+  }
+  BCHK(hipMemcpy(B.chunks_d, chunks.data(), sizeof(sc::Chunk) * chunks.size(),
+                 hipMemcpyHostToDevice));
+  BCHK(hipMemcpy(B.first_d, first.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+  BCHK(hipMemcpy(B.count_d, count.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+  BCHK(hipMemcpy(B.info_d, rinfo.data(), sizeof(sc::RedInfo) * n, hipMemcpyHostToDevice));
+  BCHK(hipMemcpy(B.rd_d, rd.data(), sizeof(sc::RampDev) * n, hipMemcpyHostToDevice));
+  BCHK(hipMemcpy(B.ck_d, ck.data(), sizeof(sc::Ckpt) * n, hipMemcpyHostToDevice));
+  BCHK(hipMemcpy(B.pc_d, pc, sizeof(double) * n * n_pc, hipMemcpyHostToDevice));
+  BCHK(hipMemset(B.S_d, 0, sizeof(double) * n * n_pc));
+  BCHK(hipMemset(B.steps_d, 0, sizeof(long long) * n * n_pc));
+  BCHK(hipMemset(B.status_d, 0, sizeof(int) * n * n_pc));
+
+  hipEvent_t w0 = B.ev[0], w1 = B.ev[1];
+  BCHK(hipEventRecord(w0, B.stream));
+  // shared launch shape, then the initial decisions
+  if (int r = autotune(B, 6)) return r;
+  sc::RampCfg cfg{c->tol, c->bisect_rel, c->max_steps, c->check_every, n_pc};
+  BCHK(sc::launch_reduce_chunks(B.th_d, B.chunks_d, B.nchunks, B.info_d, 0, B.partials, B.probe,
+                                B.stream));
+  BCHK(sc::launch_reduce_throats(B.first_d, B.count_d, n, B.partials, B.sums, B.stream));
+  BCHK(sc::launch_ramp_begin(B.th_d, B.rd_d, B.pc_d, cfg, B.sums, n, B.stream));
+  BCHK(sc::launch_copy_requests(B.th_d, B.rd_d, B.ck_d, B.chunks_d, B.nchunks, 0, B.stream));
+  if (int r = capture_chunk(B, cfg)) return r;
+  // replay until every subdomain has finished its ramp; a bound on the
+  // replays guards against a run that would never end
+  long long max_bisect = 64;
+  const long long max_replays =
+      (long long)(n_pc + max_bisect + 2) * ((c->max_steps + c->check_every - 1) / c->check_every) +
+      16;
+  long long replays = 0;
+  const int poll = 4;
+  for (;;) {
+    for (int i = 0; i < poll; ++i) BCHK(hipGraphLaunch(B.exec, B.stream));
+    replays += poll;
+    BCHK(hipMemcpyAsync(B.nact_h, B.nact_d, sizeof(int), hipMemcpyDeviceToHost, B.stream));
+    BCHK(hipStreamSynchronize(B.stream));
+    if (*B.nact_h == 0) break;
+    if (replays > max_replays) {
+      set_err("lbm_drain_batch: ramp did not finish within %lld chunk replays", replays);
+      return LBM_ESTATE;
+    }
+  }
+  BCHK(hipEventRecord(w1, B.stream));
+  BCHK(hipEventSynchronize(w1));
+  float wall = 0.f;
+  BCHK(hipEventElapsedTime(&wall, w0, w1));
+  // results
+  std::vector<double> S((size_t)n * n_pc);
+  std::vector<long long> steps((size_t)n * n_pc);
+  std::vector<int> status((size_t)n * n_pc);
+  BCHK(hipMemcpy(rd.data(), B.rd_d, sizeof(sc::RampDev) * n, hipMemcpyDeviceToHost));
+  BCHK(hipMemcpy(S.data(), B.S_d, sizeof(double) * n * n_pc, hipMemcpyDeviceToHost));
+  BCHK(hipMemcpy(steps.data(), B.steps_d, sizeof(long long) * n * n_pc, hipMemcpyDeviceToHost));
+  BCHK(hipMemcpy(status.data(), B.status_d, sizeof(int) * n * n_pc, hipMemcpyDeviceToHost));
+  bool warn = false, failed = false;
+  long long node_updates = 0, lattice_steps = 0;
+  for (int t = 0; t < n; ++t) {
+    const sc::RampDev &R = rd[t];
+    for (int i = 0; i < n_pc; ++i) {
+      out[t].S[i] = S[(size_t)t * n_pc + i];
+      out[t].steps[i] = steps[(size_t)t * n_pc + i];
+      out[t].status[i] = status[(size_t)t * n_pc + i];
+    }
+    out[t].invaded_at = R.invaded_at;
+    out[t].n_bisect = R.n_bisect;
+    out[t].total_steps = R.total_steps;
+    if (R.invaded_at < 0) {
+      out[t].pce_lo = pc[(size_t)t * n_pc + n_pc - 1];
+      out[t].pce = NAN;
+      out[t].pce_hi = INFINITY;
+    } else {
+      out[t].pce_lo = R.lo;
+      out[t].pce_hi = R.hi;
+      out[t].pce = 0.5 * (R.lo + R.hi);
+    }
+    warn |= R.warn != 0;
+    failed |= R.failed != 0;
+    node_updates += R.total_steps * (long long)B.h[t]->N;
+    lattice_steps = std::max(lattice_steps, R.total_steps);
+  }
+  if (info) {
+    info->tx = B.sched.tx;
+    info->ty = B.sched.ty;
+    info->lz = B.sched.lz;
+    info->replays = replays;
+    info->lattice_steps = replays * c->check_every;
+    info->node_updates = node_updates;
+    info->wall_ms = wall;
+    info->n_tiles = B.ntiles;
+  }
+  if (failed) return LBM_WPARTIAL;
+  return warn ? LBM_WNOTCONV : LBM_OK;
+}
+
+}  // extern "C"

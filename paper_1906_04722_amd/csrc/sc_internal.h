@@ -81,14 +81,68 @@ hipError_t launch_export(const Dom &d, const Phys &P, const double *rres_d, doub
                          hipStream_t st);
 hipError_t launch_density(const Dom &d, const Phys &P, const double *rres_d, double *rho,
                           hipStream_t st);
-// FP64 reduction: out[0..1] masses, out[2] sum of the saturation term,
-// out[3..4] densities at the probe node (if probe >= 0)
-hipError_t launch_reduce(const Dom &d, const Phys &P, double phib, long long probe,
-                         double *partials, int n_partials, double *out, hipStream_t st);
-int reduce_blocks(size_t N);
+// chunked FP64 reduction over subdomains: each chunk is a node range of one
+// subdomain; per chunk the partial sums of rho_w, rho_nw and the saturation
+// term over fluid nodes, then per subdomain the sum of its chunks in order
+struct Chunk {
+  int throat;
+  uint32_t start, count;
+};
+struct RedInfo {
+  long long probe;  // probe node or -1
+  double phib;      // bulk order parameter of the saturation map
+};
+constexpr uint32_t kChunkNodes = 4096;
+void list_chunks(int throat, uint32_t N, std::vector<Chunk> &out);
+// partials[c][3]; probe_out[t][2] = densities at subdomain t's probe node
+hipError_t launch_reduce_chunks(const Throat *th, const Chunk *chunks, int nchunks,
+                                const RedInfo *info, int parity, double *partials,
+                                double *probe_out, hipStream_t st);
+// sums[t][3] = sum over chunks first[t] .. first[t]+count[t]-1, in order
+hipError_t launch_reduce_throats(const int *first, const int *count, int n, const double *partials,
+                                 double *sums, hipStream_t st);
 // plain copy of n_floats (a multiple of 4) floats, 16-byte aligned buffers
 hipError_t launch_copy(const float *a, float *b, size_t n_floats, hipStream_t st);
 
 bool schedule_valid(const Sched &s);
+
+// ---- device-side drainage ramp of a batch of subdomains -------------------
+enum : int { kPhaseRamp = 0, kPhaseBisect = 1, kPhaseDone = 2 };
+// copy requests executed after each ramp decision, saves before restores
+enum : int { kSaveStable = 1, kSaveMain = 2, kRestoreStable = 4, kRestoreMain = 8 };
+
+struct RampCfg {
+  double tol;        // |S(t) - S(t - every)| < tol ends a ramp point
+  double rel;        // bisection stops at (hi - lo) / hi <= rel
+  long long cap;     // steps per ramp point or bisection run
+  int every;         // steps between checks (even)
+  int n_pc;
+};
+
+struct RampDev {
+  double rho_out, dpc_drho, rho_ref;   // rho_in = rho_out + pc / dpc_drho
+  double S_old, S_stable, S_main, lo, hi, mid, stable_pc, rho_in_main;
+  long long steps_pt, total_steps;
+  unsigned int n_fluid;
+  int phase, point, invaded_at, n_bisect, req, warn, failed;
+};
+
+struct Ckpt {
+  float *stable, *main;
+};
+
+// first decision: record the initial saturation, save it as the stable
+// state, set the first inlet density
+hipError_t launch_ramp_begin(Throat *th, RampDev *rd, const double *pc, const RampCfg &cfg,
+                             const double *sums, int n, hipStream_t st);
+// one decision per subdomain after `every` steps; n_active_out[0] = number of
+// subdomains still running
+hipError_t launch_ramp_advance(Throat *th, RampDev *rd, const double *pc, const RampCfg &cfg,
+                               const double *sums, const double *probe, double *S_out,
+                               long long *steps_out, int *status_out, int n, int *n_active_out,
+                               hipStream_t st);
+// perform the copy requests of every subdomain (over the reduction chunks)
+hipError_t launch_copy_requests(const Throat *th, const RampDev *rd, const Ckpt *ck,
+                                const Chunk *chunks, int nchunks, int parity, hipStream_t st);
 
 }  // namespace sc

@@ -603,18 +603,17 @@ hipError_t launch_density(const Dom &d, const Phys &P, const double *rres_d, dou
   return hipGetLastError();
 }
 
-// ---- FP64 reductions ------------------------------------------------------------
-// Two passes with a fixed summation order (grid-stride per thread, LDS tree
-// per block, then one block over the per-block partials), so results are
-// bitwise reproducible run to run.
+// ---- FP64 reductions ------------------------------------------------------
+// Two passes with a fixed summation order (strided per thread inside a node
+// chunk, LDS tree per chunk, then the chunks of a subdomain summed in order
+// by one thread), so results are bitwise reproducible and identical whether
+// a subdomain is reduced alone or inside a batch.
 constexpr int kRedThreads = 256;
 constexpr int kRedVals = 3;
 
-int reduce_blocks(size_t N) {
-  size_t b = (N + kRedThreads * 4 - 1) / (kRedThreads * 4);
-  if (b < 1) b = 1;
-  if (b > 2048) b = 2048;
-  return (int)b;
+void list_chunks(int throat, uint32_t N, std::vector<Chunk> &out) {
+  for (uint32_t s = 0; s < N; s += kChunkNodes)
+    out.push_back(Chunk{throat, s, std::min(kChunkNodes, N - s)});
 }
 
 __device__ __forceinline__ void block_sum(double (&v)[kRedVals], double (*sh)[kRedThreads]) {
@@ -632,26 +631,42 @@ __device__ __forceinline__ void block_sum(double (&v)[kRedVals], double (*sh)[kR
   for (int i = 0; i < kRedVals; ++i) v[i] = sh[i][0];
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_reduce(Dom d, Phys P, double phib,
-                                                        long long probe, double *partials,
-                                                        double *out) {
+__global__ __launch_bounds__(kRedThreads) void k_reduce_chunks(const Throat *__restrict__ th,
+                                                               const Chunk *__restrict__ chunks,
+                                                               const RedInfo *__restrict__ info,
+                                                               int parity, double *partials,
+                                                               double *probe_out) {
   __shared__ double sh[kRedVals][kRedThreads];
+  const Chunk ch = chunks[blockIdx.x];
+  const Throat &T = th[ch.throat];
+  Dom d;
+  d.src = T.g[parity];
+  d.dst = nullptr;
+  d.mask = T.mask;
+  d.N = T.N;
+  d.nx = T.nx;
+  d.ny = T.ny;
+  d.nz = T.nz;
+  d.per = T.per;
+  const float rho_ref = T.P.rho_ref;
+  const RedInfo ri = info[ch.throat];
   double acc[kRedVals] = {0.0, 0.0, 0.0};
-  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < d.N;
-       n += (size_t)gridDim.x * blockDim.x) {
+  for (uint32_t i = threadIdx.x; i < ch.count; i += kRedThreads) {
+    const uint32_t n = ch.start + i;
     const uint32_t m = d.mask[n];
     if ((m >> kTypeShift) != kFluid) continue;
-    const int x = (int)(n % d.nx), y = (int)((n / d.nx) % d.ny), z = (int)(n / ((size_t)d.nx * d.ny));
+    const int x = (int)(n % (uint32_t)d.nx), y = (int)((n / (uint32_t)d.nx) % (uint32_t)d.ny);
+    const int z = (int)(n / ((uint32_t)d.nx * (uint32_t)d.ny));
     float v[2][19];
-    pull(d, m, (uint32_t)n, x, y, z, v);
-    const double a = (double)(float)((acc_t)P.rho_ref + sum19(v[0]));
-    const double b = (double)(float)((acc_t)P.rho_ref + sum19(v[1]));
+    pull(d, m, n, x, y, z, v);
+    const double a = (double)(float)((acc_t)rho_ref + sum19(v[0]));
+    const double b = (double)(float)((acc_t)rho_ref + sum19(v[1]));
     acc[0] += a;
     acc[1] += b;
-    acc[2] += ((a - b) / (a + b) + phib) / (2.0 * phib);
-    if ((long long)n == probe) {
-      out[3] = a;
-      out[4] = b;
+    acc[2] += ((a - b) / (a + b) + ri.phib) / (2.0 * ri.phib);
+    if ((long long)n == ri.probe) {
+      probe_out[2 * ch.throat] = a;
+      probe_out[2 * ch.throat + 1] = b;
     }
   }
   block_sum(acc, sh);
@@ -659,24 +674,221 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(Dom d, Phys P, double ph
     for (int i = 0; i < kRedVals; ++i) partials[(size_t)blockIdx.x * kRedVals + i] = acc[i];
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double *partials, int nparts,
-                                                              double *out) {
-  __shared__ double sh[kRedVals][kRedThreads];
+__global__ void k_reduce_throats(const int *first, const int *count, int n,
+                                 const double *partials, double *sums) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
   double acc[kRedVals] = {0.0, 0.0, 0.0};
-  for (int p = threadIdx.x; p < nparts; p += kRedThreads)
-    for (int i = 0; i < kRedVals; ++i) acc[i] += partials[(size_t)p * kRedVals + i];
-  block_sum(acc, sh);
-  if (threadIdx.x == 0)
-    for (int i = 0; i < kRedVals; ++i) out[i] = acc[i];
+  for (int c = first[t]; c < first[t] + count[t]; ++c)
+    for (int i = 0; i < kRedVals; ++i) acc[i] += partials[(size_t)c * kRedVals + i];
+  for (int i = 0; i < kRedVals; ++i) sums[(size_t)t * kRedVals + i] = acc[i];
 }
 
-hipError_t launch_reduce(const Dom &d, const Phys &P, double phib, long long probe,
-                         double *partials, int n_partials, double *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(n_partials), dim3(kRedThreads), 0, st, d, P, phib, probe,
-                     partials, out);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, st, partials, n_partials, out);
+hipError_t launch_reduce_chunks(const Throat *th, const Chunk *chunks, int nchunks,
+                                const RedInfo *info, int parity, double *partials,
+                                double *probe_out, hipStream_t st) {
+  if (nchunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_chunks, dim3(nchunks), dim3(kRedThreads), 0, st, th, chunks, info,
+                     parity, partials, probe_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_throats(const int *first, const int *count, int n, const double *partials,
+                                 double *sums, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_throats, dim3((n + 255) / 256), dim3(256), 0, st, first, count, n,
+                     partials, sums);
+  return hipGetLastError();
+}
+
+// ---- device-side drainage ramp (Sec. 2.2.2) ---------------------------------
+// The same decisions as the host ramp of a single subdomain, taken for every
+// subdomain of a batch between chunks of steps, so that the whole ramp runs
+// as graph replays without host decisions per subdomain or per step.
+__device__ __forceinline__ void set_inlet(Throat &T, const RampDev &R, double pc) {
+  const double rin = R.rho_out + pc / R.dpc_drho;
+  T.P.rres[0][1] = (float)rin;
+  T.P.gres[0][1] = (float)(rin - R.rho_ref);
+}
+
+__global__ void k_ramp_begin(Throat *th, RampDev *rd, const double *pc, RampCfg cfg,
+                             const double *sums, int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  RampDev R = rd[t];
+  const double S = R.n_fluid ? sums[3 * t + 2] / (double)R.n_fluid : 0.0;
+  R.phase = kPhaseRamp;
+  R.point = 0;
+  R.invaded_at = -1;
+  R.n_bisect = 0;
+  R.warn = 0;
+  R.failed = 0;
+  R.steps_pt = 0;
+  R.total_steps = 0;
+  R.S_old = S;
+  R.S_stable = S;
+  R.stable_pc = 0.0;
+  R.req = kSaveStable;
+  set_inlet(th[t], R, pc[(size_t)t * cfg.n_pc]);
+  th[t].active = 1;
+  rd[t] = R;
+}
+
+__device__ __forceinline__ void ramp_next_point(Throat &T, RampDev &R, const double *pcs,
+                                                const RampCfg &cfg, double S_now) {
+  R.point += 1;
+  if (R.point >= cfg.n_pc) {
+    R.phase = kPhaseDone;
+    T.active = 0;
+    return;
+  }
+  set_inlet(T, R, pcs[R.point]);
+  R.S_old = S_now;
+  R.steps_pt = 0;
+}
+
+__device__ __forceinline__ void ramp_trial(Throat &T, RampDev &R) {
+  R.mid = 0.5 * (R.lo + R.hi);
+  R.req |= kRestoreStable;
+  set_inlet(T, R, R.mid);
+  R.S_old = R.S_stable;
+  R.steps_pt = 0;
+}
+
+__global__ __launch_bounds__(256) void k_ramp_advance(Throat *th, RampDev *rd, const double *pc,
+                                                      RampCfg cfg, const double *sums,
+                                                      const double *probe, double *S_out,
+                                                      long long *steps_out, int *status_out,
+                                                      int n, int *n_active_out) {
+  __shared__ int cnt[256];
+  int active = 0;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    RampDev R = rd[t];
+    if (R.phase == kPhaseDone) continue;
+    Throat &T = th[t];
+    const double *pcs = pc + (size_t)t * cfg.n_pc;
+    R.req = 0;  // the previous requests have been carried out
+    const double S = R.n_fluid ? sums[3 * t + 2] / (double)R.n_fluid : 0.0;
+    const bool inv = probe[2 * t + 1] > probe[2 * t];
+    R.steps_pt += cfg.every;
+    R.total_steps += cfg.every;
+    const bool nonfin = !isfinite(S);
+    const bool conv = fabs(S - R.S_old) < cfg.tol;
+    if (!nonfin && !conv && R.steps_pt < cfg.cap) {
+      R.S_old = S;
+      rd[t] = R;
+      ++active;
+      continue;
+    }
+    const int st = nonfin ? 2 : (conv ? 0 : 1);
+    if (R.phase == kPhaseRamp) {
+      const int i = R.point;
+      S_out[(size_t)t * cfg.n_pc + i] = S;
+      steps_out[(size_t)t * cfg.n_pc + i] = R.steps_pt;
+      status_out[(size_t)t * cfg.n_pc + i] = st;
+      R.warn |= st == 1;
+      if (nonfin) {
+        R.failed = 1;
+        R.phase = kPhaseDone;
+        T.active = 0;
+      } else if (!inv) {
+        R.req |= kSaveStable;
+        R.S_stable = S;
+        R.stable_pc = pcs[i];
+        ramp_next_point(T, R, pcs, cfg, S);
+      } else if (R.invaded_at >= 0) {
+        ramp_next_point(T, R, pcs, cfg, S);
+      } else {
+        R.invaded_at = i;
+        R.lo = i == 0 ? 0.0 : R.stable_pc;
+        R.hi = pcs[i];
+        if ((R.hi - R.lo) / R.hi > cfg.rel) {
+          R.req |= kSaveMain;
+          R.S_main = S;
+          R.rho_in_main = pcs[i];
+          R.phase = kPhaseBisect;
+          ramp_trial(T, R);
+        } else {
+          ramp_next_point(T, R, pcs, cfg, S);
+        }
+      }
+    } else {  // bisection run finished
+      R.n_bisect += 1;
+      if (nonfin) {
+        R.failed = 1;
+        R.phase = kPhaseDone;
+        T.active = 0;
+      } else {
+        if (inv) {
+          R.hi = R.mid;
+        } else {
+          R.lo = R.mid;
+          R.req |= kSaveStable;
+          R.S_stable = S;
+        }
+        if ((R.hi - R.lo) / R.hi > cfg.rel) {
+          ramp_trial(T, R);
+        } else {
+          R.req |= kRestoreMain;
+          R.phase = kPhaseRamp;
+          ramp_next_point(T, R, pcs, cfg, R.S_main);
+        }
+      }
+    }
+    if (R.phase != kPhaseDone) ++active;
+    rd[t] = R;
+  }
+  cnt[threadIdx.x] = active;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) cnt[threadIdx.x] += cnt[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) n_active_out[0] = cnt[0];
+}
+
+__global__ __launch_bounds__(256) void k_copy_requests(const Throat *__restrict__ th,
+                                                       const RampDev *__restrict__ rd,
+                                                       const Ckpt *__restrict__ ck,
+                                                       const Chunk *__restrict__ chunks,
+                                                       int parity) {
+  const Chunk c = chunks[blockIdx.x];
+  const int req = rd[c.throat].req;
+  if (!req) return;
+  const Throat &T = th[c.throat];
+  float *g = T.g[parity];
+  float *sa = ck[c.throat].stable, *ma = ck[c.throat].main;
+  const size_t N = T.N;
+  for (int q = 0; q < 38; ++q)
+    for (uint32_t i = threadIdx.x; i < c.count; i += blockDim.x) {
+      const size_t o = (size_t)q * N + c.start + i;
+      const float v = g[o];
+      if (req & kSaveStable) sa[o] = v;
+      if (req & kSaveMain) ma[o] = v;
+      if (req & kRestoreStable) g[o] = sa[o];
+      if (req & kRestoreMain) g[o] = ma[o];
+    }
+}
+
+hipError_t launch_ramp_begin(Throat *th, RampDev *rd, const double *pc, const RampCfg &cfg,
+                             const double *sums, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_ramp_begin, dim3((n + 255) / 256), dim3(256), 0, st, th, rd, pc, cfg, sums,
+                     n);
+  return hipGetLastError();
+}
+
+hipError_t launch_ramp_advance(Throat *th, RampDev *rd, const double *pc, const RampCfg &cfg,
+                               const double *sums, const double *probe, double *S_out,
+                               long long *steps_out, int *status_out, int n, int *n_active_out,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_ramp_advance, dim3(1), dim3(256), 0, st, th, rd, pc, cfg, sums, probe,
+                     S_out, steps_out, status_out, n, n_active_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_requests(const Throat *th, const RampDev *rd, const Ckpt *ck,
+                                const Chunk *chunks, int nchunks, int parity, hipStream_t st) {
+  if (nchunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_requests, dim3(nchunks), dim3(256), 0, st, th, rd, ck, chunks, parity);
   return hipGetLastError();
 }
 

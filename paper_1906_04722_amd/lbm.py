@@ -54,6 +54,13 @@ class lbm_drain_result(ctypes.Structure):
                 ("S", _dp), ("steps", _llp), ("status", _ip)]
 
 
+class lbm_batch_info(ctypes.Structure):
+    _fields_ = [("tx", ctypes.c_int), ("ty", ctypes.c_int), ("lz", ctypes.c_int),
+                ("n_tiles", ctypes.c_int), ("replays", ctypes.c_longlong),
+                ("lattice_steps", ctypes.c_longlong), ("node_updates", ctypes.c_longlong),
+                ("wall_ms", ctypes.c_double)]
+
+
 # exported name -> (restype, argtypes)
 SIGNATURES = {
     "lbm_throat_init": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.POINTER(ctypes.c_void_p)]),
@@ -71,6 +78,9 @@ SIGNATURES = {
     "lbm_drain_throat": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_int,
                                         ctypes.POINTER(lbm_conv),
                                         ctypes.POINTER(lbm_drain_result)]),
+    "lbm_drain_batch": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(lbm_params), _dp, ctypes.c_int,
+                                       ctypes.POINTER(lbm_conv), ctypes.POINTER(lbm_drain_result),
+                                       ctypes.POINTER(lbm_batch_info)]),
     "lbm_time_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_longlong, _dp]),
     "lbm_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "lbm_get_schedule": (ctypes.c_int, [ctypes.c_void_p, _ip, _ip, _ip]),
@@ -255,6 +265,40 @@ class Throat:
         _check(lib().lbm_get_schedule(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
                "lbm_get_schedule")
         return a.value, b.value, c.value
+
+
+def drain_batch(probs, pcs, tol=1e-6, check_every=100, max_steps=100000, bisect_rel=0.005):
+    """Batched drainage of many subdomains (lbm_drain_batch).  probs: list of
+    problem descriptions; pcs: array [n][n_pc].  Returns (list of result
+    dicts like Throat.drain, info dict)."""
+    n = len(probs)
+    pcs = np.ascontiguousarray(pcs, dtype=np.float64).reshape(n, -1)
+    n_pc = pcs.shape[1]
+    P = (lbm_params * n)()
+    keep = []
+    for i, pr in enumerate(probs):
+        P[i], k = make_params(pr)
+        keep.append(k)
+    S = np.zeros((n, n_pc))
+    steps = np.zeros((n, n_pc), dtype=np.int64)
+    status = np.zeros((n, n_pc), dtype=np.int32)
+    R = (lbm_drain_result * n)()
+    for i in range(n):
+        R[i].S = S[i].ctypes.data_as(_dp)
+        R[i].steps = steps[i].ctypes.data_as(_llp)
+        R[i].status = status[i].ctypes.data_as(_ip)
+    c = lbm_conv(float(tol), int(check_every), int(max_steps), float(bisect_rel))
+    info = lbm_batch_info()
+    rc = _check(lib().lbm_drain_batch(n, P, _dptr(pcs), n_pc, ctypes.byref(c), R,
+                                      ctypes.byref(info)), "lbm_drain_batch")
+    out = [dict(S=S[i], steps=steps[i], status=status[i], pce=R[i].pce, pce_lo=R[i].pce_lo,
+                pce_hi=R[i].pce_hi, invaded_at=R[i].invaded_at, n_bisect=R[i].n_bisect,
+                total_steps=R[i].total_steps) for i in range(n)]
+    inf = dict(tx=info.tx, ty=info.ty, lz=info.lz, n_tiles=info.n_tiles, replays=info.replays,
+               lattice_steps=info.lattice_steps, node_updates=info.node_updates,
+               wall_ms=info.wall_ms, warning=rc)
+    del keep
+    return out, inf
 
 
 def bw_probe(nbytes=4 << 30, reps=20):
