@@ -31,6 +31,13 @@ BYTES_PER_FLUID_NODE = 304   # 2 components x 19 FP32 populations, read + write
 GAMMA = synth.GAMMA_LAPLACE  # interfacial tension of the model (Laplace fit)
 N_PC = 20
 CONV = dict(tol=1e-6, check_every=100, max_steps=20000, bisect_rel=0.005)
+# batched drainage sample: throats cut from one seeded dense packing (radii
+# lognormal, mean 1, log-sd 0.2, porosity 0.38), 32 lu per unit radius, box
+# sides 48-128, 16-point ramp, entry pressure bracketed to 1 %
+BATCH_THROATS = 24
+BATCH_SINGLES = 4
+BATCH_N_PC = 16
+BATCH_CONV = dict(tol=1e-6, check_every=100, max_steps=4000, bisect_rel=0.01)
 KERNEL_SRC = os.path.join(ROOT, "paper_1906_04722_amd", "csrc", "sc_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_c2_96_traffic.txt")
 
@@ -95,6 +102,40 @@ def cpu_baseline(p, budget_s=12.0):
             "sample": f"96^3 throat, {n} FP64 steps at a fixed inlet density ({dt:.1f} s)"}
 
 
+def batch_leg(n_throats=BATCH_THROATS, n_single=BATCH_SINGLES):
+    """Batched drainage of packing throats in one lbm_drain_batch call, and the
+    first few of the same throats drained one at a time (lbm_drain_throat,
+    autotuned) on the same GPU for comparison."""
+    probs, rins, summ = synth.packing_throats(n_throats=n_throats, seed=3)
+    pcs = np.array([synth.pc_ramp(GAMMA, ri, BATCH_N_PC) for ri in rins])
+    t0 = time.perf_counter()
+    out, info = lbm.drain_batch(probs, pcs, **BATCH_CONV)
+    dt = time.perf_counter() - t0
+    ok = sum(1 for o in out if o["invaded_at"] >= 0
+             and (o["pce_hi"] - o["pce_lo"]) <= BATCH_CONV["bisect_rel"] * o["pce_hi"])
+    fl = info["fluid_updates"] / (info["wall_ms"] * 1e-3)
+    t1 = time.perf_counter()
+    single_steps = 0
+    for p, pc in zip(probs[:n_single], pcs[:n_single]):
+        g = lbm.Throat(p)
+        g.autotune(20)
+        single_steps += g.drain(pc, **BATCH_CONV)["total_steps"]
+        g.close()
+    dt1 = time.perf_counter() - t1
+    gbs = fl * BYTES_PER_FLUID_NODE / 1e9
+    return {"workload": f"{n_throats} throats cut from a seeded dense packing ({summ['n_spheres']} "
+                        "spheres, radii lognormal mean 1 sigma 0.2, porosity 0.38), 32 lu per unit "
+                        f"radius, sides 48-128, {BATCH_N_PC}-point ramp, cap "
+                        f"{BATCH_CONV['max_steps']} steps per point, p_c^e bracket 1 %",
+            "throats": n_throats, "box_nodes": int(sum(p.n_nodes for p in probs)),
+            "throats_per_s": round(n_throats / dt, 3), "wall_s": round(dt, 2),
+            "pce_bracketed_1pct": ok, "fluid_MLUPS": round(fl / 1e6, 1),
+            "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "schedule": [info["tx"], info["ty"], info["lz"]], "graph_replays": info["replays"],
+            "single_throat_drains": {"throats": n_single, "throats_per_s": round(n_single / dt1, 3),
+                                     "lattice_steps": int(single_steps)}}
+
+
 def dense_512(steps=10):
     """The same fused step on a 512^3 periodic fluid box (HBM-bound shape)."""
     n = 512
@@ -119,6 +160,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported "
@@ -180,6 +222,8 @@ def main():
                      "alg_bytes_per_launch": alg_bytes},
     }
     line["copy_probe_GBps"] = round(lbm.bw_probe(4 << 30, 10), 1)
+    if not a.no_batch:
+        line["batch"] = batch_leg()
     if not a.no_dense:
         line["dense_512"] = dense_512()
     if not a.no_cpu:

@@ -190,6 +190,7 @@ typedef struct {
   long long replays;        /* graph replays (chunks of check_every steps)   */
   long long lattice_steps;  /* fused-step launches issued                    */
   long long node_updates;   /* sum over subdomains of active steps x nodes   */
+  long long fluid_updates;  /* the same with fluid nodes only                */
   double wall_ms;           /* device time from the first to the last kernel */
 } lbm_batch_info;
 
@@ -221,7 +222,8 @@ int lbm_time_steps(lbm_throat_t h, long long nsteps, double *ms);
 int lbm_step_timer(lbm_throat_t h, int enable, double *total_ms, long long *launches);
 
 /* Launch shape of the fused step: tile (tx, ty) in {(32, 4), (32, 8),
- * (64, 4)}, z-segment length lz (>= 1).  0 keeps the current value. */
+ * (64, 4), (16, 4), (16, 8), (8, 8)}, z-segment length lz (>= 1).  0 keeps
+ * the current value. */
 int lbm_set_schedule(lbm_throat_t h, int tx, int ty, int lz);
 
 /* Autotune the launch shape for this subdomain: time `trial_steps` fused

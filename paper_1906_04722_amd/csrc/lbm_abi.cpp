@@ -809,12 +809,11 @@ int lbm_autotune(lbm_throat_t h, int trial_steps, int *tx, int *ty, int *lz) {
   }
   // candidate launch shapes; every trial reads g[cur] and writes g[1-cur]
   // without flipping, so the state is untouched
-  static const int shapes[3][2] = {{32, 4}, {32, 8}, {64, 4}};
   static const int lzs[7] = {1, 2, 4, 8, 16, 32, 64};
   const sc::Sched keep = h->sched;
   sc::Sched best = keep;
   double best_ms = INFINITY;
-  for (const auto &sh : shapes)
+  for (const auto &sh : sc::kShapes)
     for (int l : lzs) {
       if (l > h->nz) continue;
       h->sched = sc::Sched{sh[0], sh[1], l};

@@ -104,11 +104,10 @@ int build_tiles(Batch &B, const sc::Sched &s) {
 // time candidate launch shapes over the whole batch (fixed parity: the
 // trials never change the state) and keep the fastest
 int autotune(Batch &B, int trial_steps) {
-  static const int shapes[3][2] = {{32, 4}, {32, 8}, {64, 4}};
   static const int lzs[5] = {1, 2, 4, 8, 16};
   sc::Sched best = B.sched;
   double best_ms = INFINITY;
-  for (const auto &sh : shapes)
+  for (const auto &sh : sc::kShapes)
     for (int l : lzs) {
       const sc::Sched s{sh[0], sh[1], l};
       if (int r = build_tiles(B, s)) return r;
@@ -297,7 +296,7 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
   BCHK(hipMemcpy(steps.data(), B.steps_d, sizeof(long long) * n * n_pc, hipMemcpyDeviceToHost));
   BCHK(hipMemcpy(status.data(), B.status_d, sizeof(int) * n * n_pc, hipMemcpyDeviceToHost));
   bool warn = false, failed = false;
-  long long node_updates = 0, lattice_steps = 0;
+  long long node_updates = 0, fluid_updates = 0, lattice_steps = 0;
   for (int t = 0; t < n; ++t) {
     const sc::RampDev &R = rd[t];
     for (int i = 0; i < n_pc; ++i) {
@@ -320,6 +319,7 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
     warn |= R.warn != 0;
     failed |= R.failed != 0;
     node_updates += R.total_steps * (long long)B.h[t]->N;
+    fluid_updates += R.total_steps * (long long)B.h[t]->n_fluid;
     lattice_steps = std::max(lattice_steps, R.total_steps);
   }
   if (info) {
@@ -329,6 +329,7 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
     info->replays = replays;
     info->lattice_steps = replays * c->check_every;
     info->node_updates = node_updates;
+    info->fluid_updates = fluid_updates;
     info->wall_ms = wall;
     info->n_tiles = B.ntiles;
   }

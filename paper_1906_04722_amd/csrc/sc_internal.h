@@ -40,6 +40,11 @@ struct Sched {
   int tx, ty, lz;
 };
 
+// tile shapes (tx, ty) the fused step is built for; lz is free (>= 1).  The
+// narrow shapes fit thin prism subdomains with fewer solid columns per tile.
+constexpr int kNumShapes = 6;
+constexpr int kShapes[kNumShapes][2] = {{32, 4}, {32, 8}, {64, 4}, {16, 4}, {16, 8}, {8, 8}};
+
 // one subdomain as the fused step sees it: both population buffers, the
 // mask, the size, the tile grid of the launch schedule and the parameters
 // (a launch covers the tiles of one or many of these)

@@ -373,7 +373,10 @@ __global__ __launch_bounds__(TX *TY) void k_step(const Throat *__restrict__ thro
 
 bool schedule_valid(const Sched &s) {
   // (64, 8) and (32, 16) would need 2 x 78 KB of LDS staging: not offered
-  return ((s.tx == 32 && (s.ty == 4 || s.ty == 8)) || (s.tx == 64 && s.ty == 4)) && s.lz >= 1;
+  if (s.lz < 1) return false;
+  for (int i = 0; i < kNumShapes; ++i)
+    if (s.tx == kShapes[i][0] && s.ty == kShapes[i][1]) return true;
+  return false;
 }
 
 template <int TX, int TY>
@@ -392,6 +395,11 @@ hipError_t launch_step(const Throat *th, const TileRef *tiles, int ntiles, int t
     if (ty == 4) return step_as<32, 4>(th, tiles, ntiles, parity, st);
     return step_as<32, 8>(th, tiles, ntiles, parity, st);
   }
+  if (tx == 16) {
+    if (ty == 4) return step_as<16, 4>(th, tiles, ntiles, parity, st);
+    return step_as<16, 8>(th, tiles, ntiles, parity, st);
+  }
+  if (tx == 8) return step_as<8, 8>(th, tiles, ntiles, parity, st);
   return step_as<64, 4>(th, tiles, ntiles, parity, st);
 }
 

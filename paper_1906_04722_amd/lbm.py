@@ -58,7 +58,7 @@ class lbm_batch_info(ctypes.Structure):
     _fields_ = [("tx", ctypes.c_int), ("ty", ctypes.c_int), ("lz", ctypes.c_int),
                 ("n_tiles", ctypes.c_int), ("replays", ctypes.c_longlong),
                 ("lattice_steps", ctypes.c_longlong), ("node_updates", ctypes.c_longlong),
-                ("wall_ms", ctypes.c_double)]
+                ("fluid_updates", ctypes.c_longlong), ("wall_ms", ctypes.c_double)]
 
 
 # exported name -> (restype, argtypes)
@@ -296,7 +296,7 @@ def drain_batch(probs, pcs, tol=1e-6, check_every=100, max_steps=100000, bisect_
                 total_steps=R[i].total_steps) for i in range(n)]
     inf = dict(tx=info.tx, ty=info.ty, lz=info.lz, n_tiles=info.n_tiles, replays=info.replays,
                lattice_steps=info.lattice_steps, node_updates=info.node_updates,
-               wall_ms=info.wall_ms, warning=rc)
+               fluid_updates=info.fluid_updates, wall_ms=info.wall_ms, warning=rc)
     del keep
     return out, inf
 
