@@ -13,6 +13,7 @@
 // the store of the post-collision state.
 #include <algorithm>
 
+#include "geom.h"
 #include "sc_internal.h"
 
 namespace sc {
@@ -426,22 +427,7 @@ void list_tiles(const uint8_t *types, int nx, int ny, int nz, int tx, int ty, in
 }
 
 // ---- geometry ----------------------------------------------------------------
-// Node classes from spheres and the prism closure; predicates in FP64 with
-// every product and sum rounded separately (no fused multiply-add), so the
-// mask does not depend on the compiler's contraction choices.
-__device__ __forceinline__ bool in_sphere(double x, double y, double z, const double *s) {
-  const double dx = __dsub_rn(x, s[0]), dy = __dsub_rn(y, s[1]), dz = __dsub_rn(z, s[2]);
-  double d2 = __dmul_rn(dx, dx);
-  d2 = __dadd_rn(d2, __dmul_rn(dy, dy));
-  d2 = __dadd_rn(d2, __dmul_rn(dz, dz));
-  return d2 <= __dmul_rn(s[3], s[3]);
-}
-
-__device__ __forceinline__ double edge_fn(const double *P, const double *Q, double x, double y) {
-  return __dsub_rn(__dmul_rn(__dsub_rn(Q[0], P[0]), __dsub_rn(y, P[1])),
-                   __dmul_rn(__dsub_rn(Q[1], P[1]), __dsub_rn(x, P[0])));
-}
-
+// Node classes from spheres and the prism closure (predicates in geom.h).
 __global__ void k_voxelize(const double *sph, int ns, int prism, int i0, int i1, int i2, int nx,
                            int ny, int nz, int res_z, uint8_t *types) {
   const size_t N = (size_t)nx * ny * nz;
@@ -449,13 +435,9 @@ __global__ void k_voxelize(const double *sph, int ns, int prism, int i0, int i1,
        n += (size_t)gridDim.x * blockDim.x) {
     const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((size_t)nx * ny));
     bool solid = false;
-    for (int i = 0; i < ns && !solid; ++i) solid = in_sphere(x, y, z, sph + 4 * i);
+    for (int i = 0; i < ns && !solid; ++i) solid = geom::in_sphere(x, y, z, sph + 4 * i);
     if (!solid && prism) {
-      const double *A = sph + 4 * i0, *B = sph + 4 * i1, *C = sph + 4 * i2;
-      const double o = edge_fn(A, B, C[0], C[1]);
-      const double e1 = edge_fn(A, B, x, y), e2 = edge_fn(B, C, x, y), e3 = edge_fn(C, A, x, y);
-      const bool in = o > 0 ? (e1 >= 0 && e2 >= 0 && e3 >= 0) : (e1 <= 0 && e2 <= 0 && e3 <= 0);
-      solid = !in;
+      solid = !geom::in_prism(sph + 4 * i0, sph + 4 * i1, sph + 4 * i2, x, y);
     }
     uint8_t t = kFluid;
     if (solid) t = kSolid;

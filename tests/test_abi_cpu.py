@@ -1,11 +1,11 @@
 """Host-side checks of the HIP library that need no GPU: it loads, exports
-every entry point that include/lbm_abi.h declares, and the Python binding
-names the same set."""
+every entry point that the headers under include/ declare, and the Python
+bindings name the same set."""
 import ctypes
 import os
 import re
 
-from paper_1906_04722_amd import lbm
+from paper_1906_04722_amd import lbm, surrogate
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -35,7 +35,19 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_binding_covers_the_header():
-    assert declared_entry_points() == set(lbm.SIGNATURES)
+    assert declared_entry_points() == set(lbm.SIGNATURES) | set(surrogate.SIGNATURES)
+    assert not set(lbm.SIGNATURES) & set(surrogate.SIGNATURES)
+
+
+def test_surrogate_arguments_rejected_without_gpu_work():
+    L = surrogate.lib()
+    h = ctypes.c_void_p()
+    assert L.lbm_surrogate_create(0, 1, None, ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert L.lbm_surrogate_create(17, 1, None, ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert b"members" in L.lbm_last_error()
+    assert L.lbm_surrogate_predict(None, 1, None, None, None) == lbm.LBM_EINVAL
+    assert L.lbm_surrogate_members(None) == 0
+    L.lbm_surrogate_free(None)
 
 
 def test_invalid_arguments_rejected_without_gpu_work():

@@ -1,0 +1,170 @@
+"""The surrogate's HIP kernels against the FP64 reference (oracle/mlp.py).
+
+BF16 products with FP32 accumulation against FP64: forward outputs and
+gradients agree norm-wise within 2e-2 relative; against the reference
+evaluated on the same BF16-rounded weights and inputs the forward agrees
+within 1e-2.  The descriptor's occupancy is bit-exact (the same FP64
+predicates in the same order); its geometry values agree to 1e-14."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+def _sg():
+    from paper_1906_04722_amd import surrogate
+    return surrogate
+
+
+def _bf16(a):
+    return torch.tensor(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _members(k, seed=0, scale=None):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(k):
+        w = np.zeros(mlp.n_params())
+        for W, b in mlp.unpack(w):
+            W[:] = rng.uniform(-1, 1, W.shape) * np.sqrt(3.0 / W.shape[1])
+            b[:] = rng.normal(0, 0.1, b.shape)
+        out.append(w.astype(np.float32).astype(np.float64))
+    return out
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _bf16_weights(w):
+    w = w.copy()
+    for W, _ in mlp.unpack(w):
+        W[:] = _bf16(W)
+    return w
+
+
+@pytest.mark.parametrize("n", [1, 150])
+def test_forward_matches_reference(n):
+    sg = _sg()
+    ws = _members(2, seed=1)
+    m = sg.Surrogate(members=2, seed=5)
+    for z, w in enumerate(ws):
+        m.set_params(z, w)
+        assert np.array_equal(m.get_params(z), w.astype(np.float32))
+    X = np.random.default_rng(2).normal(size=(n, 80))
+    y = m.forward(X)
+    for z, w in enumerate(ws):
+        ref = mlp.forward(w, X)[0]
+        ref_b = mlp.forward(_bf16_weights(w), _bf16(X))[0]
+        print("member", z, "rel vs fp64", _rel(y[z], ref), "vs bf16-rounded", _rel(y[z], ref_b))
+        assert _rel(y[z], ref_b) <= 1e-2
+        assert _rel(y[z], ref) <= 2e-2
+
+
+def test_gradients_match_reference():
+    sg = _sg()
+    ws = _members(3, seed=3)
+    m = sg.Surrogate(members=3)
+    for z, w in enumerate(ws):
+        m.set_params(z, w)
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=(200, 80))   # several 64-row tiles with a ragged tail
+    T = rng.normal(size=(200, 17))
+    g, loss = m.grad(X, T)
+    for z, w in enumerate(ws):
+        Y, cache = mlp.forward(w, X)
+        gr = mlp.backward(w, cache, Y, T)
+        assert abs(loss[z] - mlp.mse(Y, T)) <= 2e-2 * mlp.mse(Y, T)
+        # norm-wise per parameter block (W_l, b_l)
+        o = 0
+        for l in range(4):
+            nin, nout = mlp.LAYERS[l], mlp.LAYERS[l + 1]
+            for size in (nout * nin, nout):
+                e = _rel(g[z, o:o + size].astype(np.float64), gr[o:o + size])
+                print("member", z, "layer", l, "block", size, "rel", e)
+                assert e <= 2e-2
+                o += size
+
+
+def test_training_follows_reference():
+    """Same data, initial weights and sample order: the GPU's loss history
+    and trained predictions follow the FP64 reference's."""
+    sg = _sg()
+    rng = np.random.default_rng(7)
+    n, epochs, batch = 96, 4, 32
+    X = rng.normal(size=(n, 80)) * 2.0 + 1.0
+    T = np.tanh(X[:, :17] - X[:, 17:34]) * 3.0 + 0.5
+    ws = _members(2, seed=8)
+    order = np.stack([np.stack([rng.permutation(n) for _ in range(2)]) for _ in range(epochs)])
+    m = sg.Surrogate(members=2)
+    for z, w in enumerate(ws):
+        m.set_params(z, w)
+    hist = m.train(X, T, epochs=epochs, batch=batch, lr=1e-3, order=order)
+    ref_w = [w.copy() for w in ws]
+    xs, ts, ref_hist = mlp.train(ref_w, X, T, order, batch, 1e-3, epochs)
+    print("gpu", hist, "ref", ref_hist)
+    assert np.allclose(hist, ref_hist, rtol=3e-2)
+    xmu, xsd, tmu, tsd = m.get_stats()
+    assert np.allclose(xmu, xs[0], rtol=1e-12, atol=1e-12) and np.allclose(xsd, xs[1], rtol=1e-12)
+    assert np.allclose(tmu, ts[0], rtol=1e-12, atol=1e-12) and np.allclose(tsd, ts[1], rtol=1e-12)
+    mean, std = m.predict(X[:40])
+    rmean, rstd = mlp.predict(ref_w, xs, ts, X[:40])
+    print("predict rel", _rel(mean, rmean))
+    assert _rel(mean, rmean) <= 3e-2
+    # the moved parameters follow the reference's moves
+    for z in range(2):
+        d_gpu = m.get_params(z).astype(np.float64) - ws[z]
+        d_ref = ref_w[z] - ws[z]
+        print("update rel", _rel(d_gpu, d_ref))
+        assert _rel(d_gpu, d_ref) <= 0.2
+
+
+def test_descriptor_bit_exact():
+    sg = _sg()
+    probs, _, _ = synth.packing_throats(n_throats=12, n_spheres=200, seed=11, res=8.0,
+                                        side_range=(24, 64))
+    probs.append(synth.c2_problem())
+    probs.append(synth.c1_problem())
+    F = sg.describe(probs)
+    for p, f in zip(probs, F):
+        ref = mlp.descriptor(p.spheres, p.nx, p.ny, p.nz, p.prism_ids)
+        assert np.array_equal(f[16:], ref[16:])
+        assert np.allclose(f[:16], ref[:16], rtol=1e-14, atol=1e-14)
+
+
+def test_predict_and_fallback_to_lbm():
+    sg = _sg()
+    from paper_1906_04722_amd import lbm
+    probs, rins, _ = synth.packing_throats(n_throats=6, n_spheres=200, seed=11, res=8.0,
+                                           side_range=(24, 40))
+    pcs = np.array([synth.pc_ramp(synth.GAMMA_LAPLACE, r, 16) for r in rins])
+    ws = _members(2, seed=9)
+    m = sg.Surrogate(members=2)
+    for z, w in enumerate(ws):
+        m.set_params(z, w)
+    F = np.stack([mlp.descriptor(p.spheres, p.nx, p.ny, p.nz, p.prism_ids) for p in probs])
+    xmu, xsd = F.mean(0), np.where(F.std(0) < 1e-12, 1.0, F.std(0))
+    tmu, tsd = np.full(17, 0.3), np.full(17, 0.05)
+    m.set_stats(xmu, xsd, tmu, tsd)
+    mean, std = m.predict(F)
+    rmean, rstd = mlp.predict(ws, (xmu, xsd), (tmu, tsd), F)
+    assert _rel(mean, rmean) <= 2e-2
+    assert np.allclose(std, rstd, rtol=0.1, atol=2e-3)
+    conv = dict(tol=1e-5, check_every=50, max_steps=400, bisect_rel=0.05)
+    # threshold 0 forces every throat to the LBM; a huge one keeps them all
+    out, info = m.pce(probs, pcs, threshold=1e9, **conv)
+    assert info["n_fallback"] == 0 and not out["used_fallback"].any()
+    rbar = np.array([p.spheres[:3, 3].mean() for p in probs])
+    assert np.allclose(out["pce"], mean[:, 0] / rbar, rtol=1e-12)
+    assert np.allclose(out["curve"], mean[:, 1:], rtol=1e-12)
+    out0, info0 = m.pce(probs, pcs, threshold=0.0, **conv)
+    assert info0["n_fallback"] == len(probs) and out0["used_fallback"].all()
+    ref, _ = lbm.drain_batch(probs, pcs, **conv)
+    for i, r in enumerate(ref):
+        assert np.array_equal(out0["curve"][i], r["S"])
+        assert (np.isnan(out0["pce"][i]) and np.isnan(r["pce"])) or out0["pce"][i] == r["pce"]
+        assert out0["pce_std"][i] == 0.0
