@@ -25,6 +25,7 @@ import numpy as np  # noqa: E402
 
 import synth  # noqa: E402
 from paper_1906_04722_amd import lbm  # noqa: E402
+from paper_1906_04722_amd import surrogate  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, vendor figure
 BYTES_PER_FLUID_NODE = 304   # 2 components x 19 FP32 populations, read + write
@@ -38,6 +39,14 @@ BATCH_THROATS = 24
 BATCH_SINGLES = 4
 BATCH_N_PC = 16
 BATCH_CONV = dict(tol=1e-6, check_every=100, max_steps=4000, bisect_rel=0.01)
+# learned surrogate: trained on throats of one packing drained by the batched
+# LBM, evaluated on throats of another packing against the plain LBM
+SG_TRAIN, SG_TEST, SG_INFER = 512, 256, 100000
+SG_RES, SG_SIDES = 12.0, (24, 64)
+SG_CONV = dict(tol=1e-6, check_every=100, max_steps=1500, bisect_rel=0.01)
+SG_FIT = dict(epochs=200, batch=64, lr=1e-3, seed=2)
+SG_THRESHOLD = 0.02
+BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix cores, vendor figure
 KERNEL_SRC = os.path.join(ROOT, "paper_1906_04722_amd", "csrc", "sc_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_c2_96_traffic.txt")
 
@@ -136,6 +145,83 @@ def batch_leg(n_throats=BATCH_THROATS, n_single=BATCH_SINGLES):
                                      "lattice_steps": int(single_steps)}}
 
 
+def surrogate_leg():
+    """Train the ensemble on LBM-drained throats, then answer held-out throats
+    with surrogate + LBM fallback and compare with the plain batched LBM."""
+    def throats(seed, n):
+        probs, rins, _ = synth.packing_throats(n_throats=n, seed=seed, res=SG_RES,
+                                               side_range=SG_SIDES, amp=0)
+        return probs, np.array([synth.pc_ramp(GAMMA, r, 16) for r in rins])
+
+    tr, tr_pc = throats(5, SG_TRAIN)
+    te, te_pc = throats(6, SG_TEST)
+    t0 = time.perf_counter()
+    drains, _ = lbm.drain_batch(tr, tr_pc, **SG_CONV)
+    t_data = time.perf_counter() - t0
+    F, T, _ = surrogate.training_set(tr, drains)
+    m = surrogate.Surrogate(members=5, seed=1)
+    t0 = time.perf_counter()
+    hist = m.train(F, T, **SG_FIT)
+    t_train = time.perf_counter() - t0
+    steps = SG_FIT["epochs"] * ((len(F) + SG_FIT["batch"] - 1) // SG_FIT["batch"])
+    flops = 6.0 * surrogate.NPARAM * m.members * len(F) * SG_FIT["epochs"]
+    # held-out throats: plain LBM (reference answers) and surrogate + fallback
+    t0 = time.perf_counter()
+    ref, _ = lbm.drain_batch(te, te_pc, **SG_CONV)
+    t_lbm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res, info = m.pce(te, te_pc, threshold=SG_THRESHOLD, **SG_CONV)
+    t_sg = time.perf_counter() - t0
+    pref = np.array([r["pce"] for r in ref])
+    ok = np.isfinite(pref) & np.isfinite(res["pce"])
+    err = np.abs(res["pce"][ok] - pref[ok]) / pref[ok]
+    acc = ok & ~res["used_fallback"]
+    err_acc = np.abs(res["pce"][acc] - pref[acc]) / pref[acc]
+    rbar_te = np.array([p.spheres[:3, 3].mean() for p in te])
+    base = np.abs(T[:, 0].mean() / rbar_te[ok] - pref[ok]) / pref[ok]
+    # the network alone (no fallback) and the accept/fallback trade-off at
+    # other thresholds (final answer: LBM where flagged, network elsewhere)
+    Fte = surrogate.describe(te)
+    mean, std = m.predict(Fte)
+    raw = mean[:, 0] / rbar_te
+    err_raw = np.abs(raw[ok] - pref[ok]) / pref[ok]
+    trade = []
+    for thr in (0.02, 0.05, 0.1, 0.2):
+        take = (std[:, 0] <= thr * np.abs(mean[:, 0]))[ok]
+        fin = np.where(take, err_raw, 0.0)
+        trade.append({"threshold": thr, "answered_by_network": round(float(take.mean()), 4),
+                      "final_err_median": round(float(np.median(fin)), 4),
+                      "final_within_1pct": round(float((fin <= 0.01).mean()), 4),
+                      "network_err_median_where_answered":
+                          round(float(np.median(err_raw[take])), 4) if take.any() else None})
+    # inference alone on many descriptor rows (the held-out rows repeated)
+    rows = np.tile(Fte, (SG_INFER // len(Fte) + 1, 1))[:SG_INFER]
+    m.predict(rows[:4096])
+    t0 = time.perf_counter()
+    m.predict(rows)
+    t_inf = time.perf_counter() - t0
+    return {"workload": f"train on {len(F)} drained throats of packing seed 5, test on "
+                        f"{SG_TEST} throats of packing seed 6 ({SG_RES:g} lu per unit radius, "
+                        f"sides {SG_SIDES[0]}-{SG_SIDES[1]}, 16-point ramp, cap "
+                        f"{SG_CONV['max_steps']}); 5 members 80-256-256-256-17, BF16 MFMA",
+            "train_data_lbm_s": round(t_data, 2), "train_s": round(t_train, 2),
+            "train_steps": steps, "train_loss": [round(float(hist[0]), 4), round(float(hist[-1]), 4)],
+            "train_TFLOPs": round(flops / t_train / 1e12, 3),
+            "train_frac_bf16_peak": round(flops / t_train / 1e12 / BF16_PEAK_TFLOPS, 6),
+            "test_throats": SG_TEST, "fallback": int(info["n_fallback"]),
+            "threshold": SG_THRESHOLD,
+            "pce_err_median": round(float(np.median(err)), 4),
+            "pce_within_1pct": round(float((err <= 0.01).mean()), 4),
+            "accepted_err_median": round(float(np.median(err_acc)), 4) if acc.any() else None,
+            "baseline_mean_err_median": round(float(np.median(base)), 4),
+            "network_err_median": round(float(np.median(err_raw)), 4),
+            "network_within_5pct": round(float((err_raw <= 0.05).mean()), 4),
+            "tradeoff": trade,
+            "throats_per_s_lbm": round(SG_TEST / t_lbm, 3),
+            "throats_per_s_surrogate_with_fallback": round(SG_TEST / t_sg, 3),
+            "inference_rows_per_s": round(SG_INFER / t_inf, 1)}
+
+
 def dense_512(steps=10):
     """The same fused step on a 512^3 periodic fluid box (HBM-bound shape)."""
     n = 512
@@ -161,6 +247,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported "
@@ -224,6 +311,8 @@ def main():
     line["copy_probe_GBps"] = round(lbm.bw_probe(4 << 30, 10), 1)
     if not a.no_batch:
         line["batch"] = batch_leg()
+    if not a.no_surrogate:
+        line["surrogate"] = surrogate_leg()
     if not a.no_dense:
         line["dense_512"] = dense_512()
     if not a.no_cpu:

@@ -210,3 +210,20 @@ class Surrogate:
                    predict_ms=info.predict_ms, lbm_ms=info.lbm_ms, lbm_wall_ms=info.lbm.wall_ms,
                    lbm_fluid_updates=info.lbm.fluid_updates, warning=rc)
         return dict(pce=pce, curve=curve, pce_std=pstd, used_fallback=used.astype(bool)), inf
+
+
+def training_set(probs, drains):
+    """Descriptors and targets of drained throats (lbm_drain_batch results):
+    features [m][80] from the GPU descriptor, targets [m][17] = (p_c^e times
+    the mean throat-sphere radius, the 16 ramp saturations), and the mask of
+    the throats kept (those whose ramp found the entry pressure)."""
+    F = describe(probs)
+    pce = np.array([d["pce"] for d in drains], dtype=np.float64)
+    S = np.stack([np.asarray(d["S"], dtype=np.float64) for d in drains])
+    if S.shape[1] != NCURVE:
+        raise ValueError(f"the surrogate's curve has {NCURVE} points, the drains {S.shape[1]}")
+    rbar = np.array([np.asarray(p.spheres, dtype=np.float64)[list(p.prism_ids), 3].mean()
+                     for p in probs])
+    ok = np.isfinite(pce)
+    T = np.column_stack([pce * rbar, S])
+    return F[ok], T[ok], ok

@@ -187,7 +187,8 @@ def _throat_problem(P, R, facet, apex, res, side_range, seed, amp):
         return None, r_in
     p = Problem(nx=nx, ny=ny, nz=nz, bc=(BC_WALLS, BC_WALLS, BC_RESERVOIR), spheres=sph,
                 prism_ids=(0, 1, 2), rho_in_nw=2.0, rho_out_w=2.0, z_front=2, probe=probe)
-    p.rho_init = layered_density(nx, ny, nz, p.z_front, p.rho_major, p.rho_minor, seed, amp)
+    if amp:
+        p.rho_init = layered_density(nx, ny, nz, p.z_front, p.rho_major, p.rho_minor, seed, amp)
     return p, r_in
 
 
@@ -196,6 +197,8 @@ def packing_throats(n_throats=512, n_spheres=600, seed=3, res=32.0, side_range=(
     """Throat problems cut from a seeded dense packing (radii lognormal, mean
     1.0, log-sd 0.2, solid fraction 0.62): `n_throats` interior facets drawn
     without replacement, each mapped into a box with sides in `side_range`.
+    amp > 0 adds the seeded +-amp density perturbation to the layered initial
+    state; amp = 0 leaves it unperturbed (no initial-density array).
     Returns (problems, incircle radii in lattice units, packing summary)."""
     x, r, L, phi, worst = dense_packing(n_spheres, seed=seed)
     P, R, I, tets = regular_triangulation(x, r, L)
