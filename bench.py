@@ -46,6 +46,10 @@ SG_RES, SG_SIDES = 12.0, (24, 64)
 SG_CONV = dict(tol=1e-6, check_every=100, max_steps=1500, bisect_rel=0.01)
 SG_FIT = dict(epochs=200, batch=64, lr=1e-3, seed=2)
 SG_THRESHOLD = 0.02
+# fully resolved sample: a dense packing filling a 512^3 box, 12-point ramp
+# with a short per-point cap (throughput measurement of the same step)
+SAMPLE_N, SAMPLE_SPHERES = 512, 1000
+SAMPLE_CONV = dict(tol=1e-6, check_every=50, max_steps=100, bisect_rel=0.01)
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix cores, vendor figure
 KERNEL_SRC = os.path.join(ROOT, "paper_1906_04722_amd", "csrc", "sc_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_c2_96_traffic.txt")
@@ -222,6 +226,36 @@ def surrogate_leg():
             "inference_rows_per_s": round(SG_INFER / t_inf, 1)}
 
 
+def sample_512():
+    """The fused step on the fully resolved 512^3 packed sample: walls, baths,
+    a 12-point drainage ramp with a short cap per point (throughput only)."""
+    p, summ = synth.packed_sample(SAMPLE_N, SAMPLE_SPHERES, seed=4)
+    g = lbm.Throat(p)
+    sched = g.autotune(4)
+    n_fluid = int((g.types() == lbm.LBM_NODE_FLUID).sum())
+    r_ins = (2.0 / np.sqrt(3.0) - 1.0) * summ["mean_radius_lu"]  # three touching spheres
+    pcs = synth.pc_ramp(GAMMA, r_ins, 12)
+    g.step_timer(1)
+    t0 = time.perf_counter()
+    out = g.drain(pcs, **SAMPLE_CONV)
+    wall = time.perf_counter() - t0
+    ms, launches = g.step_timer(-1)
+    g.close()
+    avg = ms * 1e-3 / max(launches, 1)
+    gbs = n_fluid * BYTES_PER_FLUID_NODE / avg / 1e9
+    nodes = p.nx * p.ny * p.nz
+    return {"workload": f"512^3 packed sample: {summ['spheres_in_box']} spheres in the box "
+                        f"(packing of {SAMPLE_SPHERES}, mean radius {summ['mean_radius_lu']:.1f} lu), "
+                        "walls, baths at z = 0 / 511, 12-point ramp, "
+                        f"{SAMPLE_CONV['max_steps']} steps cap per point",
+            "nodes": nodes, "fluid_nodes": n_fluid, "schedule": list(sched),
+            "lattice_steps": int(out["total_steps"]), "wall_s": round(wall, 2),
+            "ms_per_step": round(avg * 1e3, 4), "MLUPS": round(nodes / avg / 1e6, 1),
+            "fluid_MLUPS": round(n_fluid / avg / 1e6, 1), "achieved_GBps": round(gbs, 1),
+            "peak_GBps": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "S_w": [round(float(x), 5) for x in out["S"]]}
+
+
 def dense_512(steps=10):
     """The same fused step on a 512^3 periodic fluid box (HBM-bound shape)."""
     n = 512
@@ -248,6 +282,7 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-sample", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported "
@@ -315,6 +350,8 @@ def main():
         line["surrogate"] = surrogate_leg()
     if not a.no_dense:
         line["dense_512"] = dense_512()
+    if not a.no_sample:
+        line["sample_512"] = sample_512()
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(line), flush=True)

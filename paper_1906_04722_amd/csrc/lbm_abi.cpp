@@ -435,17 +435,34 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
     sph[4 * i + 2] = p->spheres[i].c[2];
     sph[4 * i + 3] = p->spheres[i].r;
   }
+  std::vector<int> bin_start, bin_ids;
+  int ncx = 0, ncy = 0, ncz = 0;
+  sc::bin_spheres(sph.data(), ns, h->nx, h->ny, h->nz, bin_start, bin_ids, ncx, ncy, ncz);
+  if (bin_ids.empty()) bin_ids.push_back(0);
+  int *bins_d = nullptr;
   ALLOC(sph_d, sizeof(double) * sph.size());
+  if (hipMalloc((void **)&bins_d, sizeof(int) * (bin_start.size() + bin_ids.size())) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(sph_d);
+    set_err("hipMalloc of the sphere bins failed");
+    return fail(LBM_ENOMEM);
+  }
   int rc = LBM_OK;
   do {
     if (hipMemcpyAsync(sph_d, sph.data(), sizeof(double) * sph.size(), hipMemcpyHostToDevice,
-                       h->stream) != hipSuccess) {
+                       h->stream) != hipSuccess ||
+        hipMemcpyAsync(bins_d, bin_start.data(), sizeof(int) * bin_start.size(),
+                       hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(bins_d + bin_start.size(), bin_ids.data(), sizeof(int) * bin_ids.size(),
+                       hipMemcpyHostToDevice, h->stream) != hipSuccess) {
       rc = LBM_EHIP;
       break;
     }
+    const sc::VoxBins bins{bins_d, bins_d + bin_start.size(), ncx, ncy, ncz};
     const int ids[3] = {p->prism_ids[0], p->prism_ids[1], p->prism_ids[2]};
     const int safe_ids[3] = {p->prism ? ids[0] : 0, p->prism ? ids[1] : 0, p->prism ? ids[2] : 0};
-    if (sc::launch_voxelize(sph_d, ns, p->prism ? 1 : 0, safe_ids, h->nx, h->ny, h->nz,
+    if (sc::launch_voxelize(sph_d, bins, p->prism ? 1 : 0, safe_ids, h->nx, h->ny, h->nz,
                             p->bc[2] == LBM_BC_RESERVOIR, h->types_d, h->stream) != hipSuccess ||
         sc::launch_links(h->types_d, h->nx, h->ny, h->nz, h->per, h->mask, h->stream) !=
             hipSuccess) {
@@ -460,12 +477,13 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
       break;
     }
   } while (0);
+  if (rc == LBM_OK && hipStreamSynchronize(h->stream) != hipSuccess) rc = LBM_EHIP;
+  (void)hipFree(sph_d);
+  (void)hipFree(bins_d);
   if (rc != LBM_OK) {
-    (void)hipFree(sph_d);
     set_err("geometry setup failed");
     return fail(rc);
   }
-  (void)hipFree(sph_d);
   long long nf = 0;
   for (size_t n = 0; n < h->N; ++n) nf += h->types[n] == sc::kFluid;
   h->n_fluid = nf;

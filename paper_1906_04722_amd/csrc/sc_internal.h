@@ -65,10 +65,22 @@ struct TileRef {
   int tile;
 };
 
+// spheres binned into cubic cells of kVoxCell nodes (CSR lists, device)
+constexpr int kVoxCell = 16;
+struct VoxBins {
+  const int *start;  // [ncells + 1]
+  const int *ids;    // sphere indices, increasing within a cell
+  int ncx, ncy, ncz;
+};
+// host side of the binning: every sphere goes to each cell that its bounding
+// box, widened by one node, meets
+void bin_spheres(const double *sph, int ns, int nx, int ny, int nz, std::vector<int> &start,
+                 std::vector<int> &ids, int &ncx, int &ncy, int &ncz);
+
 // kernel launchers (all asynchronous on `st`)
-hipError_t launch_voxelize(const double *spheres, int n_spheres, int prism, const int *prism_ids,
-                           int nx, int ny, int nz, int bc_z_reservoir, uint8_t *types,
-                           hipStream_t st);
+hipError_t launch_voxelize(const double *spheres, const VoxBins &bins, int prism,
+                           const int *prism_ids, int nx, int ny, int nz, int bc_z_reservoir,
+                           uint8_t *types, hipStream_t st);
 hipError_t launch_links(const uint8_t *types, int nx, int ny, int nz, int per, uint32_t *mask,
                         hipStream_t st);
 hipError_t launch_init(const Dom &d, const Phys &P, const double *rho_init, double rho_major,

@@ -234,3 +234,46 @@ def _incircle_3d(P, R, facet):
     e2 = np.cross(nrm, e1)
     loc = np.column_stack([(tri - c0) @ e1, (tri - c0) @ e2, np.zeros(3), R[list(facet)]])
     return throat_incircle(loc)
+
+
+def packed_sample(n=512, n_spheres=1000, seed=4, nz=None, probe_depth=6):
+    """A fully resolved sample: a seeded dense packing (radii lognormal, mean
+    1, log-sd 0.2, solid fraction 0.62) scaled so its periodic cell fills an
+    n x n x nz box (nz = n by default), its periodic images that reach into
+    the box included, walls on the four sides and baths at z = 0 (non-wetting
+    inlet) and z = nz - 1 (wetting outlet).  The invasion probe is a fluid
+    node near the outlet.  Returns (problem, packing summary)."""
+    nz = n if nz is None else nz
+    x, r, L, phi, worst = dense_packing(n_spheres, seed=seed)
+    box = np.array([n, n, nz], dtype=np.float64)
+    scale = box / L
+    # one isotropic scale keeps spheres round: the smallest axis ratio
+    s = float(scale.min())
+    pts, rad = [], []
+    for sx in (-1, 0, 1):
+        for sy in (-1, 0, 1):
+            for sz in (-1, 0, 1):
+                c = (x + L * np.array([sx, sy, sz])) * s
+                rr = r * s
+                keep = np.all((c + rr[:, None] > -1.0) & (c - rr[:, None] < box + 1.0), axis=1)
+                pts.append(c[keep])
+                rad.append(rr[keep])
+    C = np.concatenate(pts)
+    R = np.concatenate(rad)
+    sph = np.column_stack([C, R])
+    probe = None
+    cx, cy = (n - 1) // 2, (n - 1) // 2
+    for d in range(0, n // 2):
+        for q in ((cx + d, cy, nz - 1 - probe_depth), (cx, cy + d, nz - 1 - probe_depth),
+                  (cx - d, cy, nz - 1 - probe_depth), (cx, cy - d, nz - 1 - probe_depth)):
+            d2 = ((C - np.array(q, dtype=np.float64)) ** 2).sum(1)
+            if np.all(d2 > R * R + 1.0):
+                probe = tuple(int(v) for v in q)
+                break
+        if probe is not None:
+            break
+    p = Problem(nx=n, ny=n, nz=nz, bc=(BC_WALLS, BC_WALLS, BC_RESERVOIR), spheres=sph,
+                prism_ids=None, rho_in_nw=2.0, rho_out_w=2.0, z_front=2, probe=probe)
+    summary = dict(n_spheres=n_spheres, spheres_in_box=len(R), scale=s, solid_fraction=phi,
+                   max_overlap=worst, mean_radius_lu=float(r.mean() * s))
+    return p, summary
