@@ -221,9 +221,13 @@ int lbm_time_steps(lbm_throat_t h, long long nsteps, double *ms);
  * timing on / off, enable = -1 only reads. */
 int lbm_step_timer(lbm_throat_t h, int enable, double *total_ms, long long *launches);
 
-/* Launch shape of the fused step: tile (tx, ty) in {(32, 4), (32, 8),
- * (64, 4), (16, 4), (16, 8), (8, 8)}, z-segment length lz (>= 1).  0 keeps
- * the current value. */
+/* Launch shape of the step: tile (tx, ty) in {(32, 4), (32, 8), (64, 4),
+ * (16, 4), (16, 8), (8, 8)} marching a z-segment of lz (>= 1) planes in one
+ * fused pass; 0 keeps the current value.  tx = LBM_SCHED_NODE_LIST selects
+ * the node-list path instead (two passes over the non-solid nodes only, for
+ * mostly solid subdomains; ty and lz are ignored and read back as 0).  All
+ * shapes give bit-identical results. */
+#define LBM_SCHED_NODE_LIST (-1)
 int lbm_set_schedule(lbm_throat_t h, int tx, int ty, int lz);
 
 /* Autotune the launch shape for this subdomain: time `trial_steps` fused

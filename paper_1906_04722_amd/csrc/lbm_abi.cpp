@@ -89,10 +89,14 @@ int sync_desc(lbm_throat *h) {
   T.ny = h->ny;
   T.nz = h->nz;
   T.per = h->per;
-  T.ntx = (h->nx + h->sched.tx - 1) / h->sched.tx;
-  T.nty = (h->ny + h->sched.ty - 1) / h->sched.ty;
+  const bool tiled = h->sched.tx != sc::kListTx;
+  T.ntx = tiled ? (h->nx + h->sched.tx - 1) / h->sched.tx : 0;
+  T.nty = tiled ? (h->ny + h->sched.ty - 1) / h->sched.ty : 0;
   T.lz = h->sched.lz;
   T.active = 1;
+  T.list = h->list_d;
+  T.nlist = h->nlist;
+  T.rho = h->rho_d;
   T.P = h->P;
   HIPCHK(hipMemcpyAsync(h->desc_d, &h->desc, sizeof(sc::Throat), hipMemcpyHostToDevice,
                         h->stream));
@@ -220,6 +224,8 @@ void release(lbm_throat *h) {
     if (h->tev[i]) (void)hipEventDestroy(h->tev[i]);
   }
   if (h->mask) (void)hipFree(h->mask);
+  if (h->list_d) (void)hipFree(h->list_d);
+  if (h->rho_d) (void)hipFree(h->rho_d);
   if (h->types_d) (void)hipFree(h->types_d);
   if (h->rres_d) (void)hipFree(h->rres_d);
   if (h->partials) (void)hipFree(h->partials);
@@ -369,7 +375,8 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
     set_err("hipMemGetInfo failed");
     return fail(LBM_EHIP);
   }
-  const size_t need = h->N * (2 * 38 * sizeof(float) + sizeof(uint32_t) + 1) + (64u << 20);
+  const size_t need = h->N * (2 * 38 * sizeof(float) + 2 * sizeof(uint32_t) + sizeof(float2) + 1) +
+                      (64u << 20);
   if (need > free_b) {
     set_err("needs %zu bytes of device memory, %zu free", need, free_b);
     return fail(LBM_ENOMEM);
@@ -536,6 +543,25 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
   if (e != hipSuccess) {
     set_err("initial state failed: %s", hipGetErrorString(e));
     return fail(LBM_EHIP);
+  }
+  // node list of the non-solid nodes and the density array of the node-list
+  // path (solid entries stay zero: they are the stencil's solid density)
+  {
+    std::vector<uint32_t> list;
+    list.reserve((size_t)(h->N - (size_t)std::count(h->types.begin(), h->types.end(),
+                                                     (uint8_t)sc::kSolid)));
+    for (size_t n = 0; n < h->N; ++n)
+      if (h->types[n] != sc::kSolid) list.push_back((uint32_t)n);
+    h->nlist = (uint32_t)list.size();
+    ALLOC(h->list_d, sizeof(uint32_t) * std::max<size_t>(list.size(), 1));
+    ALLOC(h->rho_d, sizeof(float2) * h->N);
+    if ((!list.empty() && hipMemcpyAsync(h->list_d, list.data(), sizeof(uint32_t) * list.size(),
+                                         hipMemcpyHostToDevice, h->stream) != hipSuccess) ||
+        hipMemsetAsync(h->rho_d, 0, sizeof(float2) * h->N, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+      set_err("node list upload failed");
+      return fail(LBM_EHIP);
+    }
   }
   h->cur = 0;
   if (rebuild_tiles(h) != LBM_OK) return fail(LBM_EHIP);
@@ -809,9 +835,14 @@ int lbm_set_schedule(lbm_throat_t h, int tx, int ty, int lz) {
     return LBM_EINVAL;
   }
   sc::Sched s = h->sched;
-  if (tx) s.tx = tx;
-  if (ty) s.ty = ty;
-  if (lz) s.lz = lz;
+  if (tx == sc::kListTx) {
+    s = sc::Sched{sc::kListTx, 0, 0};
+  } else {
+    if (s.tx == sc::kListTx) s = sc::Sched{64, 4, 16};
+    if (tx) s.tx = tx;
+    if (ty) s.ty = ty;
+    if (lz) s.lz = lz;
+  }
   if (!sc::schedule_valid(s)) {
     set_err("schedule (%d, %d, %d) not supported", s.tx, s.ty, s.lz);
     return LBM_EINVAL;
@@ -850,6 +881,24 @@ int lbm_autotune(lbm_throat_t h, int trial_steps, int *tx, int *ty, int *lz) {
         best = h->sched;
       }
     }
+  {
+    // the node-list path
+    h->sched = sc::Sched{sc::kListTx, 0, 0};
+    TRY(rebuild_tiles(h));
+    for (int w = 0; w < 2; ++w)
+      HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sc::kListTx, 0, h->cur, h->stream));
+    HIPCHK(hipEventRecord(h->ev[0], h->stream));
+    for (int i = 0; i < trial_steps; ++i)
+      HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sc::kListTx, 0, h->cur, h->stream));
+    HIPCHK(hipEventRecord(h->ev[1], h->stream));
+    HIPCHK(hipEventSynchronize(h->ev[1]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = h->sched;
+    }
+  }
   h->sched = best;
   TRY(rebuild_tiles(h));
   if (tx) *tx = best.tx;

@@ -86,8 +86,9 @@ int build_tiles(Batch &B, const sc::Sched &s) {
   for (int t = 0; t < B.n; ++t) {
     const lbm_throat *x = B.h[t];
     sc::list_tiles(x->types.data(), x->nx, x->ny, x->nz, s.tx, s.ty, s.lz, t, tl);
-    B.th_h[t].ntx = (x->nx + s.tx - 1) / s.tx;
-    B.th_h[t].nty = (x->ny + s.ty - 1) / s.ty;
+    const bool tiled = s.tx != sc::kListTx;
+    B.th_h[t].ntx = tiled ? (x->nx + s.tx - 1) / s.tx : 0;
+    B.th_h[t].nty = tiled ? (x->ny + s.ty - 1) / s.ty : 0;
     B.th_h[t].lz = s.lz;
   }
   BCHK(hipStreamSynchronize(B.stream));
@@ -125,6 +126,24 @@ int autotune(Batch &B, int trial_steps) {
         best = s;
       }
     }
+  {
+    // the node-list path
+    const sc::Sched s{sc::kListTx, 0, 0};
+    if (int r = build_tiles(B, s)) return r;
+    for (int w = 0; w < 2; ++w)
+      BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream));
+    BCHK(hipEventRecord(B.ev[0], B.stream));
+    for (int i = 0; i < trial_steps; ++i)
+      BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream));
+    BCHK(hipEventRecord(B.ev[1], B.stream));
+    BCHK(hipEventSynchronize(B.ev[1]));
+    float ms = 0.f;
+    BCHK(hipEventElapsedTime(&ms, B.ev[0], B.ev[1]));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = s;
+    }
+  }
   return build_tiles(B, best);
 }
 

@@ -35,10 +35,13 @@ struct Phys {
   float gres[2][2];      // rres - rho_ref
 };
 
-// launch shape of the fused step
+// launch shape of the step: tiles of tx x ty columns marching lz planes in
+// one fused pass, or (tx = kListTx) the node-list path of two passes over
+// the non-solid nodes only (densities, then the fused pull-collide-store)
 struct Sched {
   int tx, ty, lz;
 };
+constexpr int kListTx = -1;
 
 // tile shapes (tx, ty) the fused step is built for; lz is free (>= 1).  The
 // narrow shapes fit thin prism subdomains with fewer solid columns per tile.
@@ -55,8 +58,15 @@ struct Throat {
   int nx, ny, nz, per;
   int ntx, nty, lz;      // tile grid: tiles of TX x TY nodes and lz planes
   int active;            // 0: the launch skips this subdomain
+  const uint32_t *list;  // node-list path: the non-solid nodes, ascending
+  uint32_t nlist;
+  float2 *rho;           // node-list path: densities of the current step [N]
   Phys P;
 };
+
+// node-list path: one workgroup of kListBlock threads per kListBlock
+// consecutive entries of a subdomain's node list (TileRef::tile = chunk)
+constexpr int kListBlock = 256;
 
 // one tile of work: subdomain index and packed tile coordinate
 // tix + ntx * (tiy + nty * tiz)

@@ -17,6 +17,11 @@
 #include "geom.h"
 #include "sc_internal.h"
 
+// Multiply-adds are fused only where one source expression reads a * b + c,
+// never across statements, so every kernel that shares the arithmetic below
+// (the tiled step, the node-list step, the export) rounds it identically.
+#pragma clang fp contract(on)
+
 namespace sc {
 
 // ---- D3Q19: rest; +x,-x,+y,-y,+z,-z; twelve edges, opposite pairs adjacent
@@ -119,12 +124,8 @@ __device__ __forceinline__ void pull(const Dom &d, uint32_t m, uint32_t n, int X
   pull_rec<0>(d, m, n, nx, nxy, cxm, cxp, cym, cyp, czm, czp, v);
 }
 
-// Arithmetic type of the update.  Populations are stored in FP32 (the HBM
-// bytes), but moments, forces, equilibria and the relaxation are evaluated
-// in FP64 registers: in FP32 the rounding of those intermediate results
-// drifts the diffuse interface systematically (40^3 throat: 4e-5 relative
-// population error after 200 steps against the FP64 oracle, 3e-7 with FP64
-// arithmetic), while the step stays HBM-bound either way.
+// Type of the density sums.  Populations are stored in FP32 (the HBM
+// bytes); the 19-term density sums are FP64 (see collide() for the rest).
 typedef double acc_t;
 
 __device__ __forceinline__ acc_t sum19(const float (&a)[19]) {
@@ -168,66 +169,77 @@ __device__ __forceinline__ float2 density_at(const Dom &d, const Phys &P, int X,
 // density stencil) and the adhesion force toward solid neighbours, entering
 // through the velocity shift u_eq = u' + tau F / rho.  v: pulled shifted
 // populations in, post-collision shifted populations out.
-__device__ __forceinline__ void collide(const Phys &P, uint32_t m, const acc_t (&Sw)[3],
-                                        const acc_t (&Sn)[3], float (&v)[2][19]) {
-  acc_t dr[2], rho[2], j[2][3];
+//
+// Precision: the densities (sum of the 19 populations) and the post-collision
+// rest population are FP64; momenta, forces, velocities and the 18 moving
+// equilibria are FP32.  The rest population is set to the FP64 density minus
+// the 18 moving post-collision values, so the collision conserves each
+// component's mass to FP64 rounding (the BGK update does so exactly), and
+// FP32 rounding of the weights (their FP32 sum is not exactly 1) cannot bias
+// the mass step after step.  Momenta are summed from opposite-pair
+// differences.
+__device__ __forceinline__ void collide(const Phys &P, uint32_t m, const float (&Sw)[3],
+                                        const float (&Sn)[3], float (&v)[2][19]) {
+  double drd[2];
+  float dr[2], rho[2], j[2][3];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    dr[c] = sum19(v[c]);
-    rho[c] = (acc_t)P.rho_ref + dr[c];
-    acc_t jx = 0, jy = 0, jz = 0;
+    drd[c] = sum19(v[c]);
+    dr[c] = (float)drd[c];
+    rho[c] = (float)((double)P.rho_ref + drd[c]);
+    float jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
     for (int k = 1; k < 19; ++k) {
-      if (ex(k) > 0) jx += v[c][k];
-      if (ex(k) < 0) jx -= v[c][k];
-      if (ey(k) > 0) jy += v[c][k];
-      if (ey(k) < 0) jy -= v[c][k];
-      if (ez(k) > 0) jz += v[c][k];
-      if (ez(k) < 0) jz -= v[c][k];
+      if (k > opp(k)) continue;
+      const float dk = v[c][k] - v[c][opp(k)];
+      if (ex(k)) jx += ex(k) > 0 ? dk : -dk;
+      if (ey(k)) jy += ey(k) > 0 ? dk : -dk;
+      if (ez(k)) jz += ez(k) > 0 ? dk : -dk;
     }
     j[c][0] = jx;
     j[c][1] = jy;
     j[c][2] = jz;
   }
-  // adhesion direction: sum_k w_k s(x + e_k) e_k, s(x + e_k) = cut bit of opp(k)
-  acc_t A[3] = {0, 0, 0};
+  float A[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int k = 1; k < 19; ++k) {
-    const acc_t s = (acc_t)((m >> opp(k)) & 1u) * (acc_t)wd(k);
+    const float s = (float)((m >> opp(k)) & 1u) * wf(k);
     if (ex(k)) A[0] += ex(k) > 0 ? s : -s;
     if (ey(k)) A[1] += ey(k) > 0 ? s : -s;
     if (ez(k)) A[2] += ez(k) > 0 ? s : -s;
   }
-  acc_t F[2][3];
-  const acc_t G = P.G, Ga0 = P.Gads[0], Ga1 = P.Gads[1];
+  float F[2][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    F[0][a] = -G * rho[0] * Sn[a] - Ga0 * rho[0] * A[a];
-    F[1][a] = -G * rho[1] * Sw[a] - Ga1 * rho[1] * A[a];
+    F[0][a] = -P.G * rho[0] * Sn[a] - P.Gads[0] * rho[0] * A[a];
+    F[1][a] = -P.G * rho[1] * Sw[a] - P.Gads[1] * rho[1] * A[a];
   }
-  const acc_t it0 = P.itau[0], it1 = P.itau[1];
-  const acc_t den = rho[0] * it0 + rho[1] * it1;
-  acc_t up[3];
+  const float it0 = P.itau[0], it1 = P.itau[1];
+  const float den = rho[0] * it0 + rho[1] * it1;
+  float up[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) up[a] = (j[0][a] * it0 + j[1][a] * it1) / den;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    acc_t u[3];
-    const acc_t tc = P.tau[c], itc = P.itau[c];
+    float u[3];
+    const float tc = P.tau[c], itc = P.itau[c];
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] = up[a] + tc * F[c][a] / rho[c];
-    const acc_t uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double rest = drd[c];
 #pragma unroll
-    for (int k = 0; k < 19; ++k) {
-      acc_t eu = 0;
+    for (int k = 1; k < 19; ++k) {
+      float eu = 0.f;
       if (ex(k)) eu += ex(k) > 0 ? u[0] : -u[0];
       if (ey(k)) eu += ey(k) > 0 ? u[1] : -u[1];
       if (ez(k)) eu += ez(k) > 0 ? u[2] : -u[2];
-      // f_eq - w_k rho_ref = w_k [(rho - rho_ref) + rho (3 eu + 4.5 eu^2 - 1.5 uu)]
-      const acc_t geq = (acc_t)wd(k) * (dr[c] + rho[c] * ((acc_t)3 * eu + (acc_t)4.5 * eu * eu - (acc_t)1.5 * uu));
-      const acc_t g = v[c][k];
-      v[c][k] = (float)(g - (g - geq) * itc);
+      const float geq = wf(k) * (dr[c] + rho[c] * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
+      const float g = v[c][k];
+      const float gs = g - (g - geq) * itc;
+      v[c][k] = gs;
+      rest -= (double)gs;
     }
+    v[c][0] = (float)rest;
   }
 }
 
@@ -337,11 +349,11 @@ __global__ __launch_bounds__(TX *TY) void k_step(const Throat *__restrict__ thro
       const uint32_t n = (uint32_t)x + (uint32_t)d.nx * ((uint32_t)y + (uint32_t)d.ny * (uint32_t)Z);
       const uint32_t t = mcur >> kTypeShift;
       if (t == kFluid) {
-        acc_t Sw[3] = {0, 0, 0}, Sn[3] = {0, 0, 0};
+        float Sw[3] = {0, 0, 0}, Sn[3] = {0, 0, 0};
 #pragma unroll
         for (int k = 1; k < 19; ++k) {
           const float2 rn = ring[(Z + ez(k)) & 3][ty + 1 + ey(k)][tx + 1 + ex(k)];
-          const acc_t a = (acc_t)wd(k) * (acc_t)rn.x, bb = (acc_t)wd(k) * (acc_t)rn.y;
+          const float a = wf(k) * rn.x, bb = wf(k) * rn.y;
           if (ex(k)) { Sw[0] += ex(k) > 0 ? a : -a; Sn[0] += ex(k) > 0 ? bb : -bb; }
           if (ey(k)) { Sw[1] += ey(k) > 0 ? a : -a; Sn[1] += ey(k) > 0 ? bb : -bb; }
           if (ez(k)) { Sw[2] += ez(k) > 0 ? a : -a; Sn[2] += ez(k) > 0 ? bb : -bb; }
@@ -373,7 +385,106 @@ __global__ __launch_bounds__(TX *TY) void k_step(const Throat *__restrict__ thro
   }
 }
 
+// ---- node-list path ---------------------------------------------------------
+// For subdomains where most nodes are solid (thin throat prisms, packed
+// samples) the tiles above spend their lanes on solid nodes.  Here every lane
+// owns one entry of the non-solid node list: a first pass writes each node's
+// densities (the same FP64 sums rounded to FP32 that the tiles keep in LDS),
+// the second pulls, takes the 18-neighbour density stencil from that array
+// (zero on solid nodes and beyond walls), collides and stores.  Per fluid
+// node the second pass moves the same 304 bytes as the fused step plus the
+// stencil reads, the first pass another 152 + 8.  Results are bit-identical
+// to the tiled step: the same sums, stencil order and collision.
+__device__ __forceinline__ const TileRef &list_ref(const TileRef *__restrict__ tiles, int ntiles) {
+  const int b = blockIdx.x;
+  const int q = ntiles >> 3, r = ntiles & 7, xcd = b & 7, idx = b >> 3;
+  return tiles[xcd * q + min(xcd, r) + idx];
+}
+
+__device__ __forceinline__ Dom list_dom(const Throat &T, int parity) {
+  Dom d;
+  d.src = T.g[parity];
+  d.dst = T.g[parity ^ 1];
+  d.mask = T.mask;
+  d.N = T.N;
+  d.nx = T.nx;
+  d.ny = T.ny;
+  d.nz = T.nz;
+  d.per = T.per;
+  return d;
+}
+
+__global__ __launch_bounds__(kListBlock) void k_dens_list(const Throat *__restrict__ throats,
+                                                          const TileRef *__restrict__ tiles,
+                                                          int ntiles, int parity) {
+  const TileRef tr = list_ref(tiles, ntiles);
+  const Throat &T = throats[tr.throat];
+  if (!T.active) return;
+  const uint32_t i = (uint32_t)tr.tile * kListBlock + threadIdx.x;
+  if (i >= T.nlist) return;
+  const Dom d = list_dom(T, parity);
+  const Phys &P = T.P;
+  const uint32_t n = T.list[i];
+  const uint32_t m = d.mask[n];
+  const uint32_t t = m >> kTypeShift;
+  float2 r;
+  if (t == kFluid) {
+    const uint32_t nx = (uint32_t)d.nx, nxy = nx * (uint32_t)d.ny;
+    const int Z = (int)(n / nxy), Y = (int)((n - (uint32_t)Z * nxy) / nx);
+    const int X = (int)(n - (uint32_t)Z * nxy - (uint32_t)Y * nx);
+    float v[2][19];
+    pull(d, m, n, X, Y, Z, v);
+    r = make_float2((float)((acc_t)P.rho_ref + sum19(v[0])), (float)((acc_t)P.rho_ref + sum19(v[1])));
+  } else if (t == kResIn) {
+    r = make_float2(P.rres[0][0], P.rres[0][1]);
+  } else {
+    r = make_float2(P.rres[1][0], P.rres[1][1]);
+  }
+  T.rho[n] = r;
+}
+
+__global__ __launch_bounds__(kListBlock) void k_step_list(const Throat *__restrict__ throats,
+                                                          const TileRef *__restrict__ tiles,
+                                                          int ntiles, int parity) {
+  const TileRef tr = list_ref(tiles, ntiles);
+  const Throat &T = throats[tr.throat];
+  if (!T.active) return;
+  const uint32_t i = (uint32_t)tr.tile * kListBlock + threadIdx.x;
+  if (i >= T.nlist) return;
+  const Dom d = list_dom(T, parity);
+  const Phys &P = T.P;
+  const uint32_t n = T.list[i];
+  const uint32_t m = d.mask[n];
+  const uint32_t t = m >> kTypeShift;
+  float v[2][19];
+  if (t == kFluid) {
+    const uint32_t nx = (uint32_t)d.nx, nxy = nx * (uint32_t)d.ny;
+    const int Z = (int)(n / nxy), Y = (int)((n - (uint32_t)Z * nxy) / nx);
+    const int X = (int)(n - (uint32_t)Z * nxy - (uint32_t)Y * nx);
+    pull(d, m, n, X, Y, Z, v);
+    float Sw[3] = {0, 0, 0}, Sn[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 1; k < 19; ++k) {
+      const long long nb = node_of(d, X + ex(k), Y + ey(k), Z + ez(k));
+      const float2 rn = nb < 0 ? make_float2(0.f, 0.f) : T.rho[nb];
+      const float a = wf(k) * rn.x, bb = wf(k) * rn.y;
+      if (ex(k)) { Sw[0] += ex(k) > 0 ? a : -a; Sn[0] += ex(k) > 0 ? bb : -bb; }
+      if (ey(k)) { Sw[1] += ey(k) > 0 ? a : -a; Sn[1] += ey(k) > 0 ? bb : -bb; }
+      if (ez(k)) { Sw[2] += ez(k) > 0 ? a : -a; Sn[2] += ez(k) > 0 ? bb : -bb; }
+    }
+    collide(P, m, Sw, Sn, v);
+  } else {
+    const int b = t == kResIn ? 0 : 1;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int k = 0; k < 19; ++k) v[c][k] = wf(k) * P.gres[b][c];
+  }
+  store_node(d, n, v);
+}
+
 bool schedule_valid(const Sched &s) {
+  if (s.tx == kListTx) return true;  // node-list path
   // (64, 8) and (32, 16) would need 2 x 78 KB of LDS staging: not offered
   if (s.lz < 1) return false;
   for (int i = 0; i < kNumShapes; ++i)
@@ -393,6 +504,14 @@ static hipError_t step_as(const Throat *th, const TileRef *tiles, int ntiles, in
 hipError_t launch_step(const Throat *th, const TileRef *tiles, int ntiles, int tx, int ty,
                        int parity, hipStream_t st) {
   if (!schedule_valid(Sched{tx, ty, 1})) return hipErrorInvalidValue;
+  if (tx == kListTx) {
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dens_list, dim3((unsigned)ntiles), dim3(kListBlock), 0, st, th, tiles,
+                       ntiles, parity);
+    hipLaunchKernelGGL(k_step_list, dim3((unsigned)ntiles), dim3(kListBlock), 0, st, th, tiles,
+                       ntiles, parity);
+    return hipGetLastError();
+  }
   if (tx == 32) {
     if (ty == 4) return step_as<32, 4>(th, tiles, ntiles, parity, st);
     return step_as<32, 8>(th, tiles, ntiles, parity, st);
@@ -407,6 +526,13 @@ hipError_t launch_step(const Throat *th, const TileRef *tiles, int ntiles, int t
 
 void list_tiles(const uint8_t *types, int nx, int ny, int nz, int tx, int ty, int lz, int throat,
                 std::vector<TileRef> &out) {
+  if (tx == kListTx) {  // node-list path: chunks of kListBlock non-solid nodes
+    const size_t N = (size_t)nx * ny * nz;
+    size_t nl = 0;
+    for (size_t n = 0; n < N; ++n) nl += types[n] != kSolid;
+    for (size_t c = 0; c * kListBlock < nl; ++c) out.push_back(TileRef{throat, (int)c});
+    return;
+  }
   const int ntx = (nx + tx - 1) / tx, nty = (ny + ty - 1) / ty, ntz = (nz + lz - 1) / lz;
   // liveness of each (x-tile, y-tile) cell of every plane, then of every z-segment
   std::vector<uint8_t> cell((size_t)ntx * nty * nz, 0);

@@ -18,6 +18,7 @@ LBM_WNOTCONV = 1
 LBM_BC_PERIODIC, LBM_BC_WALLS, LBM_BC_RESERVOIR = 0, 1, 2
 LBM_NODE_FLUID, LBM_NODE_SOLID, LBM_NODE_RES_IN, LBM_NODE_RES_OUT = 0, 1, 2, 3
 LBM_PT_CONVERGED, LBM_PT_NOT_CONVERGED, LBM_PT_NONFINITE = 0, 1, 2
+LBM_SCHED_NODE_LIST = -1
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)

@@ -101,7 +101,7 @@ def test_schedules_agree_bitwise():
     p = _ragged_problem()
     ref = None
     for tx, ty, lz in [(64, 4, 16), (32, 4, 3), (32, 8, 29), (64, 4, 1), (32, 8, 7), (64, 4, 2), (16, 4, 5),
-                       (16, 8, 1), (8, 8, 9)]:
+                       (16, 8, 1), (8, 8, 9), (lbm.LBM_SCHED_NODE_LIST, 0, 0)]:
         g = lbm.Throat(p)
         g.set_schedule(tx, ty, lz)
         g.step(30)
