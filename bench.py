@@ -55,6 +55,11 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1906_04722_amd", "csrc", "sc_kernels.hip"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_c2_96_traffic.txt")
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result line is the only stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_sha():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
@@ -124,6 +129,7 @@ def batch_leg(n_throats=BATCH_THROATS, n_single=BATCH_SINGLES):
     t0 = time.perf_counter()
     out, info = lbm.drain_batch(probs, pcs, **BATCH_CONV)
     dt = time.perf_counter() - t0
+    log(f"batch: {n_throats} throats drained in {dt:.1f} s")
     ok = sum(1 for o in out if o["invaded_at"] >= 0
              and (o["pce_hi"] - o["pce_lo"]) <= BATCH_CONV["bisect_rel"] * o["pce_hi"])
     fl = info["fluid_updates"] / (info["wall_ms"] * 1e-3)
@@ -162,6 +168,7 @@ def surrogate_leg():
     t0 = time.perf_counter()
     drains, _ = lbm.drain_batch(tr, tr_pc, **SG_CONV)
     t_data = time.perf_counter() - t0
+    log(f"surrogate: training set drained ({len(tr)} throats, {t_data:.1f} s)")
     F, T, _ = surrogate.training_set(tr, drains)
     m = surrogate.Surrogate(members=5, seed=1)
     t0 = time.perf_counter()
@@ -173,6 +180,7 @@ def surrogate_leg():
     t0 = time.perf_counter()
     ref, _ = lbm.drain_batch(te, te_pc, **SG_CONV)
     t_lbm = time.perf_counter() - t0
+    log(f"surrogate: held-out throats drained by the LBM ({t_lbm:.1f} s)")
     t0 = time.perf_counter()
     res, info = m.pce(te, te_pc, threshold=SG_THRESHOLD, **SG_CONV)
     t_sg = time.perf_counter() - t0
@@ -262,13 +270,15 @@ def dense_512(steps=10):
     p = synth.Problem(nx=n, ny=n, nz=n, bc=(synth.BC_PERIODIC,) * 3, z_front=n // 2,
                       G_ads=(0.0, 0.0))
     g = lbm.Throat(p)
+    sched = g.autotune(3)
     g.step(2)
     g.sync()
     ms = g.time_steps(steps) / steps
     g.close()
     nodes = n ** 3
     gbs = nodes * BYTES_PER_FLUID_NODE / (ms * 1e-3) / 1e9
-    return {"workload": "512^3 periodic fluid box", "ms_per_step": round(ms, 4),
+    return {"workload": "512^3 periodic fluid box", "schedule": list(sched),
+            "ms_per_step": round(ms, 4),
             "MLUPS": round(nodes / ms / 1e3, 1), "achieved_GBps": round(gbs, 1),
             "peak_GBps": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
@@ -291,11 +301,15 @@ def main():
         sys.exit(2)
 
     p, pcs = c2_workload()
-    for _ in range(a.warmup):
+    for i in range(a.warmup):
         one_drain(p, pcs)
+        log(f"warmup drain {i + 1}/{a.warmup} done")
 
     t0 = time.perf_counter()
-    results = [one_drain(p, pcs) for _ in range(a.steps)]
+    results = []
+    for i in range(a.steps):
+        results.append(one_drain(p, pcs))
+        log(f"timed drain {i + 1}/{a.steps} done")
     dt = time.perf_counter() - t0
 
     total_steps = sum(r[0]["total_steps"] for r in results)
@@ -344,16 +358,16 @@ def main():
                      "alg_bytes_per_launch": alg_bytes},
     }
     line["copy_probe_GBps"] = round(lbm.bw_probe(4 << 30, 10), 1)
-    if not a.no_batch:
-        line["batch"] = batch_leg()
-    if not a.no_surrogate:
-        line["surrogate"] = surrogate_leg()
-    if not a.no_dense:
-        line["dense_512"] = dense_512()
-    if not a.no_sample:
-        line["sample_512"] = sample_512()
-    if not a.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(p)
+    legs = [("batch", a.no_batch, batch_leg), ("surrogate", a.no_surrogate, surrogate_leg),
+            ("dense_512", a.no_dense, dense_512), ("sample_512", a.no_sample, sample_512),
+            ("cpu_baseline", a.no_cpu, lambda: cpu_baseline(p))]
+    for name, skip, fn in legs:
+        if skip:
+            continue
+        log(f"{name} ...")
+        t1 = time.perf_counter()
+        line[name] = fn()
+        log(f"{name} done in {time.perf_counter() - t1:.1f} s")
     print(json.dumps(line), flush=True)
 
 

@@ -1,9 +1,12 @@
 """Profiling driver for rocprofv3 runs of the fused step, and the summary
 writer for the counter output.
 
-  python3 -m paper_1906_04722_amd.profile_run run --steps 200
-      builds the 96^3 throat, runs a 1 GiB copy twice (the counter calibration:
-      2 GiB moved per launch, known exactly) and `steps` fused steps.
+  python3 -m paper_1906_04722_amd.profile_run run --steps 200 [--autotune 20]
+      builds the 96^3 throat (or an N^3 periodic box with --workload N, or the
+      512^3 packed sample with --workload sample512), runs
+      a 1 GiB copy twice (the counter calibration: 2 GiB moved per launch,
+      known exactly) and `steps` fused steps, optionally after autotuning the
+      launch shape as the benchmark does.
   python3 -m paper_1906_04722_amd.profile_run summarize --stats S.csv
       --fetch F.csv --write W.csv --out profiles/NAME.txt --command "..."
       writes the per-launch averages of the step kernel, the copy-kernel
@@ -27,11 +30,17 @@ def cmd_run(a):
     lbm.bw_probe(COPY_BYTES, 2)
     if a.workload == "c2":
         p = synth.c2_problem()
+    elif a.workload == "sample512":
+        p, _ = synth.packed_sample(512, 1000, seed=4)
     else:
         n = int(a.workload)
         p = synth.Problem(nx=n, ny=n, nz=n, bc=(synth.BC_PERIODIC,) * 3, z_front=n // 2,
                           G_ads=(0.0, 0.0))
     g = lbm.Throat(p)
+    if a.autotune:
+        g.autotune(a.autotune)
+    if a.schedule:
+        g.set_schedule(*[int(v) for v in a.schedule.split(",")])
     g.step(a.steps)
     g.sync()
     print(f"profile_run: {a.workload}, {a.steps} steps, schedule {g.schedule()}", flush=True)
@@ -92,6 +101,10 @@ def main():
     r = sub.add_parser("run")
     r.add_argument("--steps", type=int, default=200)
     r.add_argument("--workload", default="c2")
+    r.add_argument("--autotune", type=int, default=0,
+                   help="trial steps of the launch-shape autotuner before the run (0: default shape)")
+    r.add_argument("--schedule", default="",
+                   help="launch shape tx,ty,lz to run with (e.g. the one the benchmark's autotuner picks)")
     s = sub.add_parser("summarize")
     s.add_argument("--stats", required=True)
     s.add_argument("--fetch", required=True)
