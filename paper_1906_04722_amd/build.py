@@ -7,7 +7,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsc_lbm.so")
-SOURCES = ["sc_kernels.hip", "sg_kernels.hip", "lbm_abi.cpp", "lbm_batch.cpp", "surrogate.cpp"]
+SOURCES = ["sc_kernels.hip", "sg_kernels.hip", "lbm_abi.cpp", "lbm_batch.cpp", "surrogate.cpp",
+           "network.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

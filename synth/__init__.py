@@ -14,11 +14,12 @@ from .throats import (tetra_throat, c1_problem, c2_problem, throat_incircle, pc_
                       small_throat_problem)
 from .packing import (dense_packing, regular_triangulation, interior_facets, packing_throats,
                       packed_sample)
+from .network import pore_network, pore_void_volume
 
 __all__ = [
     "Problem", "BC_PERIODIC", "BC_WALLS", "BC_RESERVOIR", "splitmix64", "uniform_pm",
     "layered_density", "flat_interface_density", "droplet_density", "tetra_throat",
     "c1_problem", "c2_problem", "small_throat_problem", "throat_incircle", "pc_ramp", "GAMMA_LAPLACE",
     "dense_packing", "regular_triangulation", "interior_facets", "packing_throats",
-    "packed_sample",
+    "packed_sample", "pore_network", "pore_void_volume",
 ]
