@@ -25,6 +25,7 @@ import numpy as np  # noqa: E402
 
 import synth  # noqa: E402
 from paper_1906_04722_amd import lbm  # noqa: E402
+from paper_1906_04722_amd import network  # noqa: E402
 from paper_1906_04722_amd import surrogate  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, vendor figure
@@ -50,6 +51,11 @@ SG_THRESHOLD = 0.02
 # with a short per-point cap (throughput measurement of the same step)
 SAMPLE_N, SAMPLE_SPHERES = 512, 1000
 SAMPLE_CONV = dict(tol=1e-6, check_every=50, max_steps=100, bisect_rel=0.01)
+# hybrid assembly: pore network of a 40-sphere packing (the paper's sample
+# size), each throat's entry pressure from the batched LBM, then the
+# network drainage with trapping
+HYB_SPHERES = 40
+HYB_CONV = dict(tol=1e-6, check_every=100, max_steps=1500, bisect_rel=0.01)
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix cores, vendor figure
 KERNEL_SRC = os.path.join(ROOT, "paper_1906_04722_amd", "csrc", "sc_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_c2_96_traffic.txt")
@@ -264,6 +270,49 @@ def sample_512():
             "S_w": [round(float(x), 5) for x in out["S"]]}
 
 
+def hybrid_leg():
+    """Hybrid drainage of a 40-sphere packing: throat entry pressures from one
+    lbm_drain_batch call, assembled by lbm_network_drain.  Facets whose
+    opening lies outside their triangle of centres have no prism subdomain;
+    they get the incircle estimate scaled by the median LBM/incircle ratio of
+    the solved throats.  Entry pressures are compared in units of the
+    interfacial tension per packing length (p_c^e * lu-per-unit / gamma)."""
+    from synth import network as net_geo
+    x, r, L, phi, _ = synth.dense_packing(HYB_SPHERES, seed=7)
+    nw = net_geo.pore_network(x, r, L)
+    probs, r_lu, scale, r_unit = net_geo.throat_problems(nw, res=SG_RES, side_range=SG_SIDES)
+    idx = [i for i, p in enumerate(probs) if p is not None]
+    pcs = np.array([synth.pc_ramp(GAMMA, r_lu[i], 16) for i in idx])
+    t0 = time.perf_counter()
+    drains, info = lbm.drain_batch([probs[i] for i in idx], pcs, **HYB_CONV)
+    t_lbm = time.perf_counter() - t0
+    k = len(probs)
+    pce = np.full(k, np.nan)
+    for i, d in zip(idx, drains):
+        # not invaded up to the top of its ramp: impassable in this sample
+        pce[i] = d["pce"] * scale[i] / GAMMA if np.isfinite(d["pce"]) else np.inf
+    solved = np.array(idx)
+    fin = solved[np.isfinite(pce[solved])]
+    ratio = float(np.median(pce[fin] * r_unit[fin] / 2.0))
+    rest = np.setdiff1d(np.arange(k), solved)
+    pce[rest] = ratio * 2.0 / r_unit[rest]
+    pressures = np.linspace(0.5 * np.min(pce), 1.05 * np.max(pce[np.isfinite(pce)]), 24)
+    t0 = time.perf_counter()
+    sw, inv, st = network.drain(nw["pore_vol"], nw["throats"], pce, pressures)
+    t_net = time.perf_counter() - t0
+    return {"workload": f"pore network of a {HYB_SPHERES}-sphere dense packing (seed 7, porosity "
+                        f"{1 - phi:.2f}): {len(nw['pore_vol'])} pores, {k} throats, {len(idx)} solved "
+                        f"by the batched LBM ({SG_RES:g} lu per unit radius, 16-point ramp, cap "
+                        f"{HYB_CONV['max_steps']}), the rest by the scaled incircle estimate",
+            "throat_lbm_s": round(t_lbm, 2), "throats_per_s": round(len(idx) / t_lbm, 2),
+            "lbm_fluid_MLUPS": round(info["fluid_updates"] / (info["wall_ms"] * 1e3), 1),
+            "network_ms": round(t_net * 1e3, 3), "lbm_over_incircle_median": round(ratio, 4),
+            "pressures_per_gamma": [round(float(v), 4) for v in pressures],
+            "S_w": [round(float(v), 4) for v in sw],
+            "trapped_pores": int((st == network.TRAPPED).sum()),
+            "invaded_pores": int((st == network.INVADED).sum())}
+
+
 def dense_512(steps=10):
     """The same fused step on a 512^3 periodic fluid box (HBM-bound shape)."""
     n = 512
@@ -293,6 +342,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-sample", action="store_true")
+    ap.add_argument("--no-hybrid", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported "
@@ -359,6 +409,7 @@ def main():
     }
     line["copy_probe_GBps"] = round(lbm.bw_probe(4 << 30, 10), 1)
     legs = [("batch", a.no_batch, batch_leg), ("surrogate", a.no_surrogate, surrogate_leg),
+            ("hybrid_40", a.no_hybrid, hybrid_leg),
             ("dense_512", a.no_dense, dense_512), ("sample_512", a.no_sample, sample_512),
             ("cpu_baseline", a.no_cpu, lambda: cpu_baseline(p))]
     for name, skip, fn in legs:

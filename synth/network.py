@@ -112,3 +112,24 @@ def pore_network(x, r, L):
         apex.append(np.concatenate([P[v], [R[v]]]))
     return dict(pore_vol=pore_vol, pore_z=pore_z, throats=np.array(throats, dtype=np.int64),
                 facets=np.array(facets), apex=np.array(apex))
+
+
+def throat_problems(nw, res=12.0, side_range=(24, 64), amp=0.0, seed=7):
+    """LBM subdomains of the network's throats: each facet with the apex of
+    its downstream pore, mapped into a box as the packing throats are
+    (synth.packing).  Returns (problems, incircle radii in lattice units,
+    lattice units per packing length unit); a throat whose opening lies
+    outside its triangle of centres gets None (no prism subdomain) and NaN
+    for the other two values.  Also returns every throat's incircle radius in
+    packing units (the opening's radius, for the incircle estimate)."""
+    from .packing import _incircle_3d, _throat_problem
+    probs, rins, scales, r_unit = [], [], [], []
+    for k, (f, a) in enumerate(zip(nw["facets"], nw["apex"])):
+        P = np.vstack([f[:, :3], a[:3]])
+        R = np.concatenate([f[:, 3], [a[3]]])
+        p, r_lu = _throat_problem(P, R, (0, 1, 2), 3, res, side_range, seed + k, amp)
+        probs.append(p)
+        rins.append(r_lu if p is not None else np.nan)
+        scales.append(p.spheres[0, 3] / R[0] if p is not None else np.nan)
+        r_unit.append(_incircle_3d(P, R, (0, 1, 2))[0])
+    return probs, np.array(rins), np.array(scales), np.array(r_unit)
