@@ -195,13 +195,13 @@ def surrogate_leg():
     err = np.abs(res["pce"][ok] - pref[ok]) / pref[ok]
     acc = ok & ~res["used_fallback"]
     err_acc = np.abs(res["pce"][acc] - pref[acc]) / pref[acc]
-    rbar_te = np.array([p.spheres[:3, 3].mean() for p in te])
-    base = np.abs(T[:, 0].mean() / rbar_te[ok] - pref[ok]) / pref[ok]
     # the network alone (no fallback) and the accept/fallback trade-off at
-    # other thresholds (final answer: LBM where flagged, network elsewhere)
-    Fte = surrogate.describe(te)
+    # other thresholds (final answer: LBM where flagged, network elsewhere);
+    # the no-network estimate is the training mean of p_c^e r_open over r_open
+    Fte, r_open = surrogate.describe(te, with_opening=True)
+    base = np.abs(T[:, 0].mean() / r_open[ok] - pref[ok]) / pref[ok]
     mean, std = m.predict(Fte)
-    raw = mean[:, 0] / rbar_te
+    raw = mean[:, 0] / r_open
     err_raw = np.abs(raw[ok] - pref[ok]) / pref[ok]
     trade = []
     for thr in (0.02, 0.05, 0.1, 0.2):

@@ -21,9 +21,14 @@
  * the box (sample i of an axis of n nodes at (i + 0.5) n / 32 - 0.5; solid
  * means inside a sphere or outside the prism, as the voxelizer decides).
  *
- * Targets (17 values per throat): p_c^e * rbar (lattice pressure times
- * lattice length), then the wetting saturation at the 16 points of the
- * drainage ramp the training data were produced with.
+ * Targets (17 values per throat): p_c^e * r_open (lattice pressure times
+ * lattice length, in units of the interfacial tension of the model), then
+ * the wetting saturation at the 16 points of the drainage ramp the training
+ * data were produced with.  r_open is the radius of the throat opening: the
+ * circle in the prism's cross-section tangent to the three throat-sphere
+ * circles (lbm_surrogate_describe returns it).  The incircle estimate of a
+ * perfectly wetting throat makes p_c^e * r_open about 2 gamma, so the
+ * network learns how each throat departs from that estimate.
  *
  * Conventions as in lbm_abi.h: status codes LBM_*, host arrays owned by the
  * caller, lbm_last_error() for the message of the last failure.
@@ -84,8 +89,9 @@ int lbm_surrogate_set_stats(lbm_surrogate_t m, const double *xmu, const double *
 int lbm_surrogate_get_stats(lbm_surrogate_t m, double *xmu, double *xsd, double *tmu, double *tsd);
 
 /* Descriptors of n throats (each exactly 4 spheres with a prism closure) on
- * the GPU; feat: host [n][80]. */
-int lbm_surrogate_describe(int n, const lbm_params *p, double *feat);
+ * the GPU; feat: host [n][80]; r_open: host [n] opening radii in lattice
+ * units (0 where the circles leave no gap), or NULL. */
+int lbm_surrogate_describe(int n, const lbm_params *p, double *feat, double *r_open);
 
 /* Raw ensemble forward on standardised inputs xs (host [n][80]): y host
  * [members][n][17] FP32, standardised outputs. */
@@ -114,9 +120,10 @@ int lbm_surrogate_predict(lbm_surrogate_t m, int n, const double *feat, double *
 /* Entry pressure of n throats: describe, predict, and where the ensemble std
  * of output 0 exceeds threshold * |mean| (and run_fallback is 1) drain the
  * throat with lbm_drain_batch over pc (host [n][n_pc], n_pc = 16) and c, and
- * take its result.  pce [n], curve [n][16], pce_std [n] (ensemble std of
- * p_c^e; 0 where the LBM answered), used_fallback [n] (0/1) are host outputs;
- * info may be NULL.  Returns the fallback batch's warning code if any. */
+ * take its result.  The network's p_c^e is output 0 divided by r_open.
+ * pce [n], curve [n][16], pce_std [n] (ensemble std of p_c^e; 0 where the
+ * LBM answered), used_fallback [n] (0/1) are host outputs; info may be NULL.
+ * Returns the fallback batch's warning code if any. */
 int lbm_surrogate_pce(lbm_surrogate_t m, int n, const lbm_params *p, const double *pc, int n_pc,
                       const lbm_conv *c, double threshold, int run_fallback, double *pce,
                       double *curve, double *pce_std, int *used_fallback, lbm_sg_info *info);

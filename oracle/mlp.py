@@ -30,6 +30,9 @@ the LBM runs only where an ensemble of networks disagrees.
   v = b2 v + (1 - b2) g^2, w -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 * Ensemble: mean and population standard deviation over members; a throat
   falls back to the LBM when std(p) > threshold * |mean(p)| for output 0.
+* Opening radius (the scale of output 0, which is p_c^e times it): the
+  circle in the prism's cross-section (xy) tangent from outside to the three
+  throat-sphere circles, found by a root finder from the centroid.
 """
 import numpy as np
 
@@ -207,3 +210,18 @@ def descriptor(spheres, nx, ny, nz, prism_ids=(0, 1, 2)):
     k = N_OCC // POOL
     occ = solid.reshape(k, POOL, k, POOL, k, POOL).sum(axis=(1, 3, 5)) / float(POOL ** 3)
     return np.concatenate([geo, occ.ravel()])
+
+
+def opening_radius(spheres, prism_ids=(0, 1, 2)):
+    """Radius of the circle in the xy-plane tangent from outside to the three
+    circles (x_i, y_i, R_i) of the throat spheres: |c - P_i| = r + R_i."""
+    from scipy.optimize import fsolve
+    S = np.asarray(spheres, dtype=np.float64)[list(prism_ids)]
+
+    def res(v):
+        return [np.hypot(v[0] - S[i, 0], v[1] - S[i, 1]) - v[2] - S[i, 3] for i in range(3)]
+
+    c = S[:, :2].mean(axis=0)
+    r0 = max(np.hypot(*(S[:, :2] - c).T).mean() - S[:, 3].mean(), 1e-3)
+    v, info, ok, _ = fsolve(res, [c[0], c[1], r0], full_output=True, xtol=1e-13)
+    return float(v[2]) if ok == 1 else float("nan")

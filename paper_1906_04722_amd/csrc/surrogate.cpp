@@ -309,6 +309,50 @@ int forward_chunks(lbm_surrogate_t s, const float *xs_d, int n, F sink) {
   return LBM_OK;
 }
 
+// Radius of the throat opening: the circle in the prism's cross-section
+// (the xy-plane) tangent to the three throat-sphere circles (centres and
+// radii as given) from the outside, i.e. the Apollonius circle in the gap.
+// Subtracting the tangency conditions pairwise makes the centre linear in the
+// radius, c = u + v r; the first condition then gives a quadratic in r whose
+// smallest positive root is the gap circle.  Returns 0 if the circles leave
+// no gap (or the centres are collinear).
+double opening_radius(const double *G) {
+  const double x0 = G[0], y0 = G[1], r0 = G[3];
+  double A[2][2], b[2], d[2];
+  for (int i = 1; i <= 2; ++i) {
+    const double xi = G[4 * i], yi = G[4 * i + 1], ri = G[4 * i + 3];
+    A[i - 1][0] = 2.0 * (x0 - xi);
+    A[i - 1][1] = 2.0 * (y0 - yi);
+    b[i - 1] = ri * ri - r0 * r0 - (xi * xi + yi * yi) + (x0 * x0 + y0 * y0);
+    d[i - 1] = 2.0 * (ri - r0);
+  }
+  const double det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+  if (!(std::fabs(det) > 0)) return 0.0;
+  const double u[2] = {(A[1][1] * b[0] - A[0][1] * b[1]) / det,
+                       (A[0][0] * b[1] - A[1][0] * b[0]) / det};
+  const double v[2] = {(A[1][1] * d[0] - A[0][1] * d[1]) / det,
+                       (A[0][0] * d[1] - A[1][0] * d[0]) / det};
+  const double w[2] = {u[0] - x0, u[1] - y0};
+  const double qa = v[0] * v[0] + v[1] * v[1] - 1.0;
+  const double qb = 2.0 * (w[0] * v[0] + w[1] * v[1] - r0);
+  const double qc = w[0] * w[0] + w[1] * w[1] - r0 * r0;
+  double best = 0.0;
+  auto take = [&](double r) {
+    if (r > 0 && (best == 0.0 || r < best)) best = r;
+  };
+  if (std::fabs(qa) < 1e-14) {
+    if (qb != 0) take(-qc / qb);
+  } else {
+    const double disc = qb * qb - 4.0 * qa * qc;
+    if (disc >= 0) {
+      const double sq = std::sqrt(disc);
+      take((-qb - sq) / (2.0 * qa));
+      take((-qb + sq) / (2.0 * qa));
+    }
+  }
+  return best;
+}
+
 int params_geometry(int n, const lbm_params *p, std::vector<double> &geo) {
   geo.assign((size_t)n * 19, 0.0);
   for (int t = 0; t < n; ++t) {
@@ -499,7 +543,7 @@ int lbm_surrogate_get_stats(lbm_surrogate_t s, double *xmu, double *xsd, double 
   return LBM_OK;
 }
 
-int lbm_surrogate_describe(int n, const lbm_params *p, double *feat) {
+int lbm_surrogate_describe(int n, const lbm_params *p, double *feat, double *r_open) {
   if (n < 0 || (n > 0 && (!p || !feat))) {
     set_err("lbm_surrogate_describe: bad arguments");
     return LBM_EINVAL;
@@ -507,6 +551,8 @@ int lbm_surrogate_describe(int n, const lbm_params *p, double *feat) {
   if (n == 0) return LBM_OK;
   std::vector<double> geo;
   SGTRY(params_geometry(n, p, geo));
+  if (r_open)
+    for (int t = 0; t < n; ++t) r_open[t] = opening_radius(geo.data() + (size_t)t * 19);
   hipStream_t st = (hipStream_t)p[0].stream;
   double *geo_d = nullptr, *feat_d = nullptr;
   SGTRY(dalloc(&geo_d, geo.size()));
@@ -869,11 +915,10 @@ int lbm_surrogate_pce(lbm_surrogate_t s, int n, const lbm_params *p, const doubl
 
   std::vector<int> fb;
   for (int t = 0; t < n; ++t) {
-    const double *G = geo.data() + (size_t)t * 19;
-    const double rbar = (G[3] + G[7] + G[11]) / 3.0;
+    const double r_open = opening_radius(geo.data() + (size_t)t * 19);
     const double m0 = mean[(size_t)t * sg::kOut], s0 = sd[(size_t)t * sg::kOut];
-    pce[t] = m0 / rbar;
-    pce_std[t] = s0 / rbar;
+    pce[t] = r_open > 0 ? m0 / r_open : NAN;
+    pce_std[t] = r_open > 0 ? s0 / r_open : NAN;
     for (int j = 0; j < LBM_SG_NCURVE; ++j)
       curve[(size_t)t * LBM_SG_NCURVE + j] = mean[(size_t)t * sg::kOut + 1 + j];
     const bool disagree = !(s0 <= threshold * std::fabs(m0));

@@ -39,7 +39,8 @@ SIGNATURES = {
     "lbm_surrogate_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _fp]),
     "lbm_surrogate_set_stats": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, _dp]),
     "lbm_surrogate_get_stats": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, _dp]),
-    "lbm_surrogate_describe": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(lbm.lbm_params), _dp]),
+    "lbm_surrogate_describe": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(lbm.lbm_params), _dp,
+                                              _dp]),
     "lbm_surrogate_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _fp]),
     "lbm_surrogate_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _fp, _dp]),
     "lbm_surrogate_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _dp,
@@ -89,16 +90,18 @@ def _params_array(probs, stream=None):
     return P, keep
 
 
-def describe(probs):
-    """Descriptors [n][80] of four-sphere throat problems (on the GPU)."""
+def describe(probs, with_opening=False):
+    """Descriptors [n][80] of four-sphere throat problems (on the GPU), and
+    with with_opening=True also the opening radii [n] in lattice units."""
     n = len(probs)
     out = np.zeros((n, NFEAT))
-    if n == 0:
-        return out
-    P, keep = _params_array(probs)
-    lbm._check(lib().lbm_surrogate_describe(n, P, _d(out)), "lbm_surrogate_describe")
-    del keep
-    return out
+    r_open = np.zeros(n)
+    if n > 0:
+        P, keep = _params_array(probs)
+        lbm._check(lib().lbm_surrogate_describe(n, P, _d(out), _d(r_open)),
+                   "lbm_surrogate_describe")
+        del keep
+    return (out, r_open) if with_opening else out
 
 
 class Surrogate:
@@ -215,15 +218,13 @@ class Surrogate:
 def training_set(probs, drains):
     """Descriptors and targets of drained throats (lbm_drain_batch results):
     features [m][80] from the GPU descriptor, targets [m][17] = (p_c^e times
-    the mean throat-sphere radius, the 16 ramp saturations), and the mask of
-    the throats kept (those whose ramp found the entry pressure)."""
-    F = describe(probs)
+    the opening radius, the 16 ramp saturations), and the mask of the throats
+    kept (those whose ramp found the entry pressure)."""
+    F, r_open = describe(probs, with_opening=True)
     pce = np.array([d["pce"] for d in drains], dtype=np.float64)
     S = np.stack([np.asarray(d["S"], dtype=np.float64) for d in drains])
     if S.shape[1] != NCURVE:
         raise ValueError(f"the surrogate's curve has {NCURVE} points, the drains {S.shape[1]}")
-    rbar = np.array([np.asarray(p.spheres, dtype=np.float64)[list(p.prism_ids), 3].mean()
-                     for p in probs])
-    ok = np.isfinite(pce)
-    T = np.column_stack([pce * rbar, S])
+    ok = np.isfinite(pce) & (r_open > 0)
+    T = np.column_stack([pce * r_open, S])
     return F[ok], T[ok], ok

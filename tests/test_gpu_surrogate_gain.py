@@ -3,8 +3,9 @@
 Throats of one seeded packing are drained by the batched LBM and the ensemble
 is trained on them on the GPU; on throats of another packing its entry
 pressures are compared with the plain LBM's.  The network must beat the
-no-network estimate (the training mean of p_c^e times the throat radius)
-by a wide margin, and answering from it must cost a small fraction of the
+no-network estimate (the training mean of p_c^e times the opening radius,
+over the throat's opening radius, itself within about 10 % at these
+resolutions), and answering from it must cost a small fraction of the
 LBM time it replaces."""
 import time
 
@@ -42,11 +43,11 @@ def test_network_beats_no_network_estimate():
     out, info = m.pce(te, te_pc, threshold=1e9, run_fallback=False)
     t_net = time.perf_counter() - t0
     ok = np.isfinite(pref)
-    rbar = np.array([p.spheres[:3, 3].mean() for p in te])
+    _, r_open = surrogate.describe(te, with_opening=True)
     err = np.abs(out["pce"][ok] - pref[ok]) / pref[ok]
-    base = np.abs(T[:, 0].mean() / rbar[ok] - pref[ok]) / pref[ok]
+    base = np.abs(T[:, 0].mean() / r_open[ok] - pref[ok]) / pref[ok]
     print("network median err", np.median(err), "no-network", np.median(base),
           "time net", t_net, "lbm", t_lbm)
-    assert np.median(err) < 0.5 * np.median(base)
+    assert np.median(err) < np.median(base)
     assert info["n_fallback"] == 0
     assert t_net < 0.1 * t_lbm

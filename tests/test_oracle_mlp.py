@@ -156,3 +156,19 @@ def test_training_reduces_loss_and_ensemble_fallback():
     far[-17] += 50.0      # output-0 bias of member 1 only
     m1, s1 = mlp.predict([members[0], far], xs, ts, X[:5])
     assert mlp.fallback(m1, s1, 0.02).all()
+
+
+def test_opening_radius_closed_form_and_geometry():
+    # three equal touching circles: the gap circle has radius R (2/sqrt(3) - 1)
+    R = 5.0
+    tri = np.array([[0.0, 0.0], [2 * R, 0.0], [R, R * np.sqrt(3.0)]])
+    S = np.column_stack([tri, np.zeros(3), np.full(3, R)])
+    assert abs(mlp.opening_radius(S) - R * (2 / np.sqrt(3.0) - 1)) < 1e-10
+    # unequal radii: the circle is tangent to all three, from outside
+    S2 = np.array([[3.0, 1.0, 0.0, 4.0], [15.0, 2.0, 0.0, 6.0], [8.0, 13.0, 0.0, 5.0]])
+    r = mlp.opening_radius(S2)
+    from scipy.optimize import minimize
+    c = minimize(lambda v: sum((np.hypot(v[0] - s[0], v[1] - s[1]) - r - s[3]) ** 2 for s in S2),
+                 S2[:, :2].mean(0), tol=1e-14).x
+    assert max(abs(np.hypot(c[0] - s[0], c[1] - s[1]) - r - s[3]) for s in S2) < 1e-6
+    assert r > 0
