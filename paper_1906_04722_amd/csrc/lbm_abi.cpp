@@ -172,6 +172,11 @@ int validate(const lbm_params *p) {
             (long long)p->nx * p->ny * p->nz);
     return LBM_EINVAL;
   }
+  if ((long long)p->nx * p->ny > sc::kMaxPlaneNodes) {
+    set_err("plane of %lld nodes: at most %lld nodes per z-plane",
+            (long long)p->nx * p->ny, sc::kMaxPlaneNodes);
+    return LBM_EINVAL;
+  }
   for (int a = 0; a < 3; ++a) {
     const int b = p->bc[a];
     const bool ok = b == LBM_BC_PERIODIC || b == LBM_BC_WALLS || (a == 2 && b == LBM_BC_RESERVOIR);
@@ -235,6 +240,7 @@ void release(lbm_throat *h) {
   if (h->chunk_count_d) (void)hipFree(h->chunk_count_d);
   if (h->desc_d) (void)hipFree(h->desc_d);
   if (h->tiles_d) (void)hipFree(h->tiles_d);
+  if (h->zper_d) (void)hipFree(h->zper_d);
   if (h->red_d) (void)hipFree(h->red_d);
   if (h->red_h) (void)hipHostFree(h->red_h);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -244,7 +250,7 @@ void release(lbm_throat *h) {
 int run_steps(lbm_throat *h, long long n) {
   for (long long i = 0; i < n; ++i) {
     hipError_t e = sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, h->sched.tx, h->sched.ty,
-                                   h->cur, h->stream);
+                                   h->cur, h->stream, h->zper_d, h->n_zper);
     if (e != hipSuccess) {
       set_err("step launch failed: %s", hipGetErrorString(e));
       return LBM_EHIP;
@@ -277,7 +283,8 @@ int set_rho_in(lbm_throat *h, double r) {
 }
 
 int copy_state(lbm_throat *h, float *dst, const float *src) {
-  HIPCHK(hipMemcpyAsync(dst, src, sizeof(float) * 38 * h->N, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(dst, src, sizeof(float) * sc::pop_elems(h->nx, h->ny, h->nz),
+                        hipMemcpyDeviceToDevice, h->stream));
   return LBM_OK;
 }
 
@@ -375,7 +382,8 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
     set_err("hipMemGetInfo failed");
     return fail(LBM_EHIP);
   }
-  const size_t need = h->N * (2 * 38 * sizeof(float) + 2 * sizeof(uint32_t) + sizeof(float2) + 1) +
+  const size_t pop_bytes = sizeof(float) * sc::pop_elems(h->nx, h->ny, h->nz);
+  const size_t need = 2 * pop_bytes + h->N * (2 * sizeof(uint32_t) + sizeof(float2) + 1) +
                       (64u << 20);
   if (need > free_b) {
     set_err("needs %zu bytes of device memory, %zu free", need, free_b);
@@ -397,11 +405,20 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
       return fail(LBM_ENOMEM);                                                 \
     }                                                                          \
   } while (0)
-  ALLOC(h->g[0], sizeof(float) * 38 * h->N);
-  ALLOC(h->g[1], sizeof(float) * 38 * h->N);
+  ALLOC(h->g[0], pop_bytes);
+  ALLOC(h->g[1], pop_bytes);
   ALLOC(h->mask, sizeof(uint32_t) * h->N);
   ALLOC(h->types_d, h->N);
   ALLOC(h->rres_d, 4 * sizeof(double));
+  if (h->per & 4) {
+    const int zero = 0;
+    ALLOC(h->zper_d, sizeof(int));
+    if (hipMemcpy(h->zper_d, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+      set_err("upload of the ghost-plane list failed");
+      return fail(LBM_EHIP);
+    }
+    h->n_zper = 1;
+  }
   {
     std::vector<sc::Chunk> ch;
     sc::list_chunks(0, (uint32_t)h->N, ch);
@@ -537,7 +554,7 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
   const sc::Dom d = dom(h, nullptr, nullptr);
   hipError_t e = sc::launch_init(d, h->P, rho_d, h->rho_major, h->rho_minor, p->z_front, h->rres_d,
                                  h->g[0], h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(h->g[1], 0, sizeof(float) * 38 * h->N, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->g[1], 0, pop_bytes, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (rho_d) (void)hipFree(rho_d);
   if (e != hipSuccess) {
@@ -712,7 +729,9 @@ int lbm_drain_throat(lbm_throat_t h, const double *pc, int n_pc, const lbm_conv 
     }
   }
   for (int i = 0; i < 2; ++i)
-    if (!h->save[i] && hipMalloc((void **)&h->save[i], sizeof(float) * 38 * h->N) != hipSuccess) {
+    if (!h->save[i] &&
+        hipMalloc((void **)&h->save[i], sizeof(float) * sc::pop_elems(h->nx, h->ny, h->nz)) !=
+            hipSuccess) {
       set_err("hipMalloc of a ramp checkpoint failed");
       return LBM_ENOMEM;
     }
@@ -868,10 +887,10 @@ int lbm_autotune(lbm_throat_t h, int trial_steps, int *tx, int *ty, int *lz) {
       h->sched = sc::Sched{sh[0], sh[1], l};
       TRY(rebuild_tiles(h));
       for (int w = 0; w < 2; ++w)
-        HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sh[0], sh[1], h->cur, h->stream));
+        HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sh[0], sh[1], h->cur, h->stream, h->zper_d, h->n_zper));
       HIPCHK(hipEventRecord(h->ev[0], h->stream));
       for (int i = 0; i < trial_steps; ++i)
-        HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sh[0], sh[1], h->cur, h->stream));
+        HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sh[0], sh[1], h->cur, h->stream, h->zper_d, h->n_zper));
       HIPCHK(hipEventRecord(h->ev[1], h->stream));
       HIPCHK(hipEventSynchronize(h->ev[1]));
       float ms = 0.f;
@@ -886,10 +905,10 @@ int lbm_autotune(lbm_throat_t h, int trial_steps, int *tx, int *ty, int *lz) {
     h->sched = sc::Sched{sc::kListTx, 0, 0};
     TRY(rebuild_tiles(h));
     for (int w = 0; w < 2; ++w)
-      HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sc::kListTx, 0, h->cur, h->stream));
+      HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sc::kListTx, 0, h->cur, h->stream, h->zper_d, h->n_zper));
     HIPCHK(hipEventRecord(h->ev[0], h->stream));
     for (int i = 0; i < trial_steps; ++i)
-      HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sc::kListTx, 0, h->cur, h->stream));
+      HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sc::kListTx, 0, h->cur, h->stream, h->zper_d, h->n_zper));
     HIPCHK(hipEventRecord(h->ev[1], h->stream));
     HIPCHK(hipEventSynchronize(h->ev[1]));
     float ms = 0.f;

@@ -30,6 +30,8 @@ struct Batch {
   sc::Throat *th_d = nullptr;
   sc::TileRef *tiles_d = nullptr;
   int ntiles = 0;
+  int *zper_d = nullptr;  // z-periodic subdomains (ghost-plane refresh)
+  int n_zper = 0;
   sc::Chunk *chunks_d = nullptr;
   int nchunks = 0;
   int *first_d = nullptr, *count_d = nullptr;
@@ -49,7 +51,7 @@ struct Batch {
   ~Batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    for (void *p : {(void *)th_d, (void *)tiles_d, (void *)chunks_d, (void *)first_d,
+    for (void *p : {(void *)th_d, (void *)tiles_d, (void *)zper_d, (void *)chunks_d, (void *)first_d,
                     (void *)count_d, (void *)info_d, (void *)partials, (void *)sums,
                     (void *)probe, (void *)rd_d, (void *)ck_d, (void *)pc_d, (void *)S_d,
                     (void *)steps_d, (void *)status_d, (void *)nact_d})
@@ -113,10 +115,10 @@ int autotune(Batch &B, int trial_steps) {
       const sc::Sched s{sh[0], sh[1], l};
       if (int r = build_tiles(B, s)) return r;
       for (int w = 0; w < 2; ++w)
-        BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream));
+        BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream, B.zper_d, B.n_zper));
       BCHK(hipEventRecord(B.ev[0], B.stream));
       for (int i = 0; i < trial_steps; ++i)
-        BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream));
+        BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream, B.zper_d, B.n_zper));
       BCHK(hipEventRecord(B.ev[1], B.stream));
       BCHK(hipEventSynchronize(B.ev[1]));
       float ms = 0.f;
@@ -131,10 +133,10 @@ int autotune(Batch &B, int trial_steps) {
     const sc::Sched s{sc::kListTx, 0, 0};
     if (int r = build_tiles(B, s)) return r;
     for (int w = 0; w < 2; ++w)
-      BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream));
+      BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream, B.zper_d, B.n_zper));
     BCHK(hipEventRecord(B.ev[0], B.stream));
     for (int i = 0; i < trial_steps; ++i)
-      BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream));
+      BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream, B.zper_d, B.n_zper));
     BCHK(hipEventRecord(B.ev[1], B.stream));
     BCHK(hipEventSynchronize(B.ev[1]));
     float ms = 0.f;
@@ -151,7 +153,8 @@ int capture_chunk(Batch &B, const sc::RampCfg &cfg) {
   BCHK(hipStreamBeginCapture(B.stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
   for (int i = 0; i < cfg.every && e == hipSuccess; ++i)
-    e = sc::launch_step(B.th_d, B.tiles_d, B.ntiles, B.sched.tx, B.sched.ty, i & 1, B.stream);
+    e = sc::launch_step(B.th_d, B.tiles_d, B.ntiles, B.sched.tx, B.sched.ty, i & 1, B.stream,
+                        B.zper_d, B.n_zper);
   if (e == hipSuccess)
     e = sc::launch_reduce_chunks(B.th_d, B.chunks_d, B.nchunks, B.info_d, 0, B.partials, B.probe,
                                  B.stream);
@@ -230,7 +233,9 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
     }
     B.h.push_back(x);
     for (int i = 0; i < 2; ++i)
-      if (!x->save[i] && hipMalloc((void **)&x->save[i], sizeof(float) * 38 * x->N) != hipSuccess) {
+      if (!x->save[i] &&
+          hipMalloc((void **)&x->save[i], sizeof(float) * sc::pop_elems(x->nx, x->ny, x->nz)) !=
+              hipSuccess) {
         set_err("lbm_drain_batch: no device memory for the checkpoints of subdomain %d", t);
         return LBM_ENOMEM;
       }
@@ -271,6 +276,15 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
   BCHK(hipMemset(B.S_d, 0, sizeof(double) * n * n_pc));
   BCHK(hipMemset(B.steps_d, 0, sizeof(long long) * n * n_pc));
   BCHK(hipMemset(B.status_d, 0, sizeof(int) * n * n_pc));
+  {
+    std::vector<int> zper;
+    for (int t = 0; t < n; ++t)
+      if (B.h[t]->per & 4) zper.push_back(t);
+    B.n_zper = (int)zper.size();
+    if (dalloc(&B.zper_d, zper.size())) return LBM_ENOMEM;
+    if (!zper.empty())
+      BCHK(hipMemcpy(B.zper_d, zper.data(), sizeof(int) * zper.size(), hipMemcpyHostToDevice));
+  }
 
   hipEvent_t w0 = B.ev[0], w1 = B.ev[1];
   BCHK(hipEventRecord(w0, B.stream));

@@ -49,6 +49,8 @@ struct lbm_throat {
   sc::TileRef *tiles_d = nullptr;
   int ntiles = 0;
   size_t tiles_cap = 0;
+  int *zper_d = nullptr;             // {0} on a z-periodic subdomain (ghost planes)
+  int n_zper = 0;
   // event-timed step launches inside the drainage ramp
   hipEvent_t tev[2] = {nullptr, nullptr};
   bool timing = false;

@@ -1,9 +1,10 @@
 // sc_kernels.hip -- gfx950 kernels of the two-component Shan-Chen D3Q19
 // update (Montella et al., Sec. 2.1, Eq. 1-5) on one pore-throat subdomain.
 //
-// Storage: shifted FP32 populations g = f - w_k rho_ref, structure of arrays
-// [component][direction][z][y][x]; x is the unit-stride axis so a wavefront
-// reads and writes 64 consecutive floats per direction.  The update is a
+// Storage: shifted FP32 populations g = f - w_k rho_ref; per row of nodes the
+// 38 populations (component-major) are consecutive runs of nx floats, x the
+// unit-stride axis so a wavefront reads and writes 64 consecutive floats per
+// population (layout and ghost planes in sc_internal.h).  The update is a
 // pull scheme: buffer `src` holds the post-collision state of step t-1 at
 // each node's own position; pulling g_k from x - e_k gives the pre-collision
 // state f(x, t) of Eq. 1.  One kernel does the whole step: pull + half-way
@@ -69,59 +70,67 @@ __device__ __forceinline__ long long node_of(const Dom &d, int X, int Y, int Z) 
 
 __device__ __forceinline__ int wrap(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
-// Pull the pre-collision populations f(x,t) - w_k rho_ref of fluid node n at
-// (X, Y, Z): g_k from x - e_k, or the reflected g_opp(k) at x itself when the
-// link to x - e_k is cut by a solid node or a wall (half-way bounce-back).
-// Addresses are a uniform plane base (scalar registers) plus a 32-bit byte
-// offset per lane: the pair of planes {k, opp(k)} is addressed from the lower
-// one, so offsets stay below 2 N * 4 bytes (N < 2^29 is enforced at init).
+// Pull the pre-collision populations f(x,t) - w_k rho_ref of the fluid node
+// at (X, Y, Z) with link bits m: g_k from x - e_k, or the reflected g_opp(k)
+// at x itself when the link to x - e_k is cut by a solid node or a wall
+// (half-way bounce-back).  Addresses are the start of plane Z - 1 (uniform
+// across a tile) plus a 32-bit byte offset per lane; with P the elements of
+// a plane and R = 38 nx those of a row, population q of the node itself is at
+// element P + Y R + q nx + X, of the source node at (1 - ez) P + Ys R + q nx
+// + Xs.  The second component's populations follow 19 rows of nx later.
+// global-memory views of the population buffers: loads and stores then take
+// a uniform 64-bit base and a 32-bit per-lane offset
+typedef const __attribute__((address_space(1))) char gcchar;
+typedef __attribute__((address_space(1))) char gchar;
+
 template <int K>
-__device__ __forceinline__ void pull_dir(const Dom &d, uint32_t m, uint32_t n, uint32_t s,
-                                         float (&v)[2][19]) {
+__device__ __forceinline__ void pull_dir(gcchar *b0, gcchar *b1, uint32_t m, uint32_t own,
+                                         uint32_t s, uint32_t nx, float (&v)[2][19]) {
   constexpr int o = opp(K);
-  constexpr int mn = K < o ? K : o;
-  const uint32_t N = (uint32_t)d.N;
   const bool cut = (m >> K) & 1u;
-  const uint32_t off = cut ? (uint32_t)(o - mn) * N + n : (uint32_t)(K - mn) * N + s;
-  const char *b0 = (const char *)(d.src + (size_t)mn * d.N);
-  const char *b1 = (const char *)(d.src + (size_t)(19 + mn) * d.N);
-  v[0][K] = *(const float *)(b0 + (size_t)(off * 4u));
-  v[1][K] = *(const float *)(b1 + (size_t)(off * 4u));
+  const uint32_t off = cut ? own + (uint32_t)o * nx : s + (uint32_t)K * nx;
+  v[0][K] = *(const __attribute__((address_space(1))) float *)(b0 + (size_t)(off * 4u));
+  v[1][K] = *(const __attribute__((address_space(1))) float *)(b1 + (size_t)(off * 4u));
 }
 
 template <int K>
-__device__ __forceinline__ uint32_t src_index(uint32_t n, uint32_t nx, uint32_t nxy, uint32_t cxm,
-                                              uint32_t cxp, uint32_t cym, uint32_t cyp,
-                                              uint32_t czm, uint32_t czp) {
+__device__ __forceinline__ uint32_t src_index(uint32_t own, uint32_t R, uint32_t P, uint32_t cxm,
+                                              uint32_t cxp, uint32_t cym, uint32_t cyp) {
   // x - e_k in modular 32-bit arithmetic; the c?? terms wrap across a
-  // periodic face (on other faces the link is cut and the value is unused)
-  uint32_t s = n;
+  // periodic x or y face (on other faces the link is cut and the value is
+  // unused); z needs no wrap thanks to the ghost planes
+  uint32_t s = own;
   if (ex(K) > 0) s = s - 1u + cxm;
   if (ex(K) < 0) s = s + 1u - cxp;
-  if (ey(K) > 0) s = s - nx + cym;
-  if (ey(K) < 0) s = s + nx - cyp;
-  if (ez(K) > 0) s = s - nxy + czm;
-  if (ez(K) < 0) s = s + nxy - czp;
+  if (ey(K) > 0) s = s - R + cym;
+  if (ey(K) < 0) s = s + R - cyp;
+  if (ez(K) > 0) s = s - P;
+  if (ez(K) < 0) s = s + P;
   return s;
 }
 
 template <int K>
-__device__ __forceinline__ void pull_rec(const Dom &d, uint32_t m, uint32_t n, uint32_t nx,
-                                         uint32_t nxy, uint32_t cxm, uint32_t cxp, uint32_t cym,
-                                         uint32_t cyp, uint32_t czm, uint32_t czp,
+__device__ __forceinline__ void pull_rec(gcchar *b0, gcchar *b1, uint32_t m, uint32_t own,
+                                         uint32_t nx, uint32_t R, uint32_t P, uint32_t cxm,
+                                         uint32_t cxp, uint32_t cym, uint32_t cyp,
                                          float (&v)[2][19]) {
-  pull_dir<K>(d, m, n, src_index<K>(n, nx, nxy, cxm, cxp, cym, cyp, czm, czp), v);
-  if constexpr (K + 1 < 19) pull_rec<K + 1>(d, m, n, nx, nxy, cxm, cxp, cym, cyp, czm, czp, v);
+  pull_dir<K>(b0, b1, m, own, src_index<K>(own, R, P, cxm, cxp, cym, cyp), nx, v);
+  if constexpr (K + 1 < 19) pull_rec<K + 1>(b0, b1, m, own, nx, R, P, cxm, cxp, cym, cyp, v);
 }
 
-__device__ __forceinline__ void pull(const Dom &d, uint32_t m, uint32_t n, int X, int Y, int Z,
+__device__ __forceinline__ void pull(const Dom &d, uint32_t m, int X, int Y, int Z,
                                      float (&v)[2][19]) {
-  const uint32_t nx = (uint32_t)d.nx, nxy = (uint32_t)d.nx * (uint32_t)d.ny;
-  const uint32_t N = (uint32_t)d.N;
+  const uint32_t nx = (uint32_t)d.nx, R = 38u * nx, P = R * (uint32_t)d.ny;
+  gcchar *b0 = (gcchar *)(d.src + (size_t)P * (size_t)Z);
+  gcchar *b1 = b0 + (size_t)19 * nx * 4;
+  uint32_t own = P + (uint32_t)Y * R + (uint32_t)X;
+  // The offsets do not depend on Z (the base does), so a z-marching loop
+  // would otherwise keep all 38 of them live in registers across planes;
+  // this opaque move makes them cheap per-plane arithmetic instead.
+  asm volatile("" : "+v"(own));
   const uint32_t cxm = X == 0 ? nx : 0u, cxp = X == d.nx - 1 ? nx : 0u;
-  const uint32_t cym = Y == 0 ? nxy : 0u, cyp = Y == d.ny - 1 ? nxy : 0u;
-  const uint32_t czm = Z == 0 ? N : 0u, czp = Z == d.nz - 1 ? N : 0u;
-  pull_rec<0>(d, m, n, nx, nxy, cxm, cxp, cym, cyp, czm, czp, v);
+  const uint32_t cym = Y == 0 ? P : 0u, cyp = Y == d.ny - 1 ? P : 0u;
+  pull_rec<0>(b0, b1, m, own, nx, R, P, cxm, cxp, cym, cyp, v);
 }
 
 // Type of the density sums.  Populations are stored in FP32 (the HBM
@@ -155,11 +164,11 @@ __device__ __forceinline__ float2 density_at(const Dom &d, const Phys &P, int X,
   if (t == kResOut) return make_float2(P.rres[1][0], P.rres[1][1]);
   int X2 = wrap(X, d.nx), Y2 = wrap(Y, d.ny), Z2 = wrap(Z, d.nz);
   if (KEEP) {
-    pull(d, m, (uint32_t)n, X2, Y2, Z2, v);
+    pull(d, m, X2, Y2, Z2, v);
     return make_float2((float)((acc_t)P.rho_ref + sum19(v[0])), (float)((acc_t)P.rho_ref + sum19(v[1])));
   } else {
     float t2[2][19];
-    pull(d, m, (uint32_t)n, X2, Y2, Z2, t2);
+    pull(d, m, X2, Y2, Z2, t2);
     return make_float2((float)((acc_t)P.rho_ref + sum19(t2[0])), (float)((acc_t)P.rho_ref + sum19(t2[1])));
   }
 }
@@ -243,14 +252,26 @@ __device__ __forceinline__ void collide(const Phys &P, uint32_t m, const float (
   }
 }
 
-__device__ __forceinline__ void store_node(const Dom &d, uint32_t n, const float (&v)[2][19]) {
+// Store the post-collision populations of the node at (X, Y, Z) (the ghost
+// planes of z-periodic subdomains are refreshed by k_ghost after the step).
+__device__ __forceinline__ void store_plane(float *plane, uint32_t own, uint32_t nx,
+                                            const float (&v)[2][19]) {
+  gchar *b = (gchar *)plane;
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int k = 0; k < 19; ++k) {
-      char *b = (char *)(d.dst + (size_t)(c * 19 + k) * d.N);
-      __builtin_nontemporal_store(v[c][k], (float *)(b + (size_t)(n * 4u)));
-    }
+    for (int k = 0; k < 19; ++k)
+      __builtin_nontemporal_store(
+          v[c][k], (__attribute__((address_space(1))) float *)(
+                       b + (size_t)((own + (uint32_t)(19 * c + k) * nx) * 4u)));
+}
+
+__device__ __forceinline__ void store_node(const Dom &d, int X, int Y, int Z,
+                                           const float (&v)[2][19]) {
+  const uint32_t nx = (uint32_t)d.nx, R = 38u * nx, P = R * (uint32_t)d.ny;
+  uint32_t own = (uint32_t)Y * R + (uint32_t)X;
+  asm volatile("" : "+v"(own));  // per-plane offsets, as in pull()
+  store_plane(d.dst + (size_t)P * (size_t)(Z + 1), own, nx, v);
 }
 
 // ---- fused step ------------------------------------------------------------
@@ -280,8 +301,11 @@ __device__ __forceinline__ void halo_slot(int h, int &hx, int &hy) {
   }
 }
 
+// At most 168 VGPRs per lane: three waves per SIMD, which the z-march needs
+// to keep enough pulls in flight.
 template <int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void k_step(const Throat *__restrict__ throats,
+__global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(3))) void k_step(
+    const Throat *__restrict__ throats,
                                                  const TileRef *__restrict__ tiles, int ntiles,
                                                  int parity) {
   constexpr int NT = TX * TY;
@@ -346,7 +370,6 @@ __global__ __launch_bounds__(TX *TY) void k_step(const Throat *__restrict__ thro
     if (ahead) rho_ahead = density_at<true>(d, P, x, y, Z + 2, nxt, mnxt);
     // 3. collide plane Z
     if (own) {
-      const uint32_t n = (uint32_t)x + (uint32_t)d.nx * ((uint32_t)y + (uint32_t)d.ny * (uint32_t)Z);
       const uint32_t t = mcur >> kTypeShift;
       if (t == kFluid) {
         float Sw[3] = {0, 0, 0}, Sn[3] = {0, 0, 0};
@@ -359,14 +382,14 @@ __global__ __launch_bounds__(TX *TY) void k_step(const Throat *__restrict__ thro
           if (ez(k)) { Sw[2] += ez(k) > 0 ? a : -a; Sn[2] += ez(k) > 0 ? bb : -bb; }
         }
         collide(P, mcur, Sw, Sn, cur);
-        store_node(d, n, cur);
+        store_node(d, x, y, Z, cur);
       } else if (t == kResIn || t == kResOut) {
         const int i = t == kResIn ? 0 : 1;
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
           for (int k = 0; k < 19; ++k) cur[c][k] = wf(k) * P.gres[i][c];
-        store_node(d, n, cur);
+        store_node(d, x, y, Z, cur);
       }
     }
     // 4. publish plane Z+2, rotate Z+1 -> registers, Z+2 -> LDS
@@ -433,7 +456,7 @@ __global__ __launch_bounds__(kListBlock) void k_dens_list(const Throat *__restri
     const int Z = (int)(n / nxy), Y = (int)((n - (uint32_t)Z * nxy) / nx);
     const int X = (int)(n - (uint32_t)Z * nxy - (uint32_t)Y * nx);
     float v[2][19];
-    pull(d, m, n, X, Y, Z, v);
+    pull(d, m, X, Y, Z, v);
     r = make_float2((float)((acc_t)P.rho_ref + sum19(v[0])), (float)((acc_t)P.rho_ref + sum19(v[1])));
   } else if (t == kResIn) {
     r = make_float2(P.rres[0][0], P.rres[0][1]);
@@ -457,11 +480,11 @@ __global__ __launch_bounds__(kListBlock) void k_step_list(const Throat *__restri
   const uint32_t m = d.mask[n];
   const uint32_t t = m >> kTypeShift;
   float v[2][19];
+  const uint32_t nx = (uint32_t)d.nx, nxy = nx * (uint32_t)d.ny;
+  const int Z = (int)(n / nxy), Y = (int)((n - (uint32_t)Z * nxy) / nx);
+  const int X = (int)(n - (uint32_t)Z * nxy - (uint32_t)Y * nx);
   if (t == kFluid) {
-    const uint32_t nx = (uint32_t)d.nx, nxy = nx * (uint32_t)d.ny;
-    const int Z = (int)(n / nxy), Y = (int)((n - (uint32_t)Z * nxy) / nx);
-    const int X = (int)(n - (uint32_t)Z * nxy - (uint32_t)Y * nx);
-    pull(d, m, n, X, Y, Z, v);
+    pull(d, m, X, Y, Z, v);
     float Sw[3] = {0, 0, 0}, Sn[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 1; k < 19; ++k) {
@@ -480,7 +503,7 @@ __global__ __launch_bounds__(kListBlock) void k_step_list(const Throat *__restri
 #pragma unroll
       for (int k = 0; k < 19; ++k) v[c][k] = wf(k) * P.gres[b][c];
   }
-  store_node(d, n, v);
+  store_node(d, X, Y, Z, v);
 }
 
 bool schedule_valid(const Sched &s) {
@@ -501,9 +524,23 @@ static hipError_t step_as(const Throat *th, const TileRef *tiles, int ntiles, in
   return hipGetLastError();
 }
 
-hipError_t launch_step(const Throat *th, const TileRef *tiles, int ntiles, int tx, int ty,
-                       int parity, hipStream_t st) {
-  if (!schedule_valid(Sched{tx, ty, 1})) return hipErrorInvalidValue;
+// Ghost planes of z-periodic subdomains after a step: plane 0 of the new
+// state is copied to plane nz, plane nz - 1 to plane -1 (two contiguous runs
+// of 38 nx ny floats).  Grid: x over the run, y over the listed subdomains.
+__global__ __launch_bounds__(256) void k_ghost(const Throat *__restrict__ throats,
+                                               const int *__restrict__ ids, int parity) {
+  const Throat &T = throats[ids[blockIdx.y]];
+  if (!T.active) return;
+  float *g = T.g[parity ^ 1];
+  const size_t P = pop_plane(T.nx, T.ny);
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < P; i += (size_t)gridDim.x * 256) {
+    g[P * (size_t)(T.nz + 1) + i] = g[P + i];
+    g[i] = g[P * (size_t)T.nz + i];
+  }
+}
+
+static hipError_t step_body(const Throat *th, const TileRef *tiles, int ntiles, int tx, int ty,
+                            int parity, hipStream_t st) {
   if (tx == kListTx) {
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_dens_list, dim3((unsigned)ntiles), dim3(kListBlock), 0, st, th, tiles,
@@ -522,6 +559,15 @@ hipError_t launch_step(const Throat *th, const TileRef *tiles, int ntiles, int t
   }
   if (tx == 8) return step_as<8, 8>(th, tiles, ntiles, parity, st);
   return step_as<64, 4>(th, tiles, ntiles, parity, st);
+}
+
+hipError_t launch_step(const Throat *th, const TileRef *tiles, int ntiles, int tx, int ty,
+                       int parity, hipStream_t st, const int *zper_ids, int n_zper) {
+  if (!schedule_valid(Sched{tx, ty, 1})) return hipErrorInvalidValue;
+  const hipError_t e = step_body(th, tiles, ntiles, tx, ty, parity, st);
+  if (e != hipSuccess || n_zper <= 0 || ntiles <= 0) return e;
+  hipLaunchKernelGGL(k_ghost, dim3(1024, (unsigned)n_zper), dim3(256), 0, st, th, zper_ids, parity);
+  return hipGetLastError();
 }
 
 void list_tiles(const uint8_t *types, int nx, int ny, int nz, int tx, int ty, int lz, int throat,
@@ -666,12 +712,22 @@ __device__ __forceinline__ double rho0_of(const uint32_t *mask, const double *rh
 
 __global__ void k_init(Dom d, double rho_ref, const double *rho_init, double maj, double mnr,
                        int z_front, const double *rres, float *g) {
+  const size_t P = pop_plane(d.nx, d.ny);
   for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < d.N;
        n += (size_t)gridDim.x * blockDim.x) {
     const int x = (int)(n % d.nx), y = (int)((n / d.nx) % d.ny), z = (int)(n / ((size_t)d.nx * d.ny));
+    // this node's row in its plane and, on a z-periodic subdomain, in the
+    // ghost plane that mirrors it
+    float *row = g + P * (size_t)(z + 1) + (size_t)y * 38 * d.nx + x;
+    float *ghost = nullptr;
+    if ((d.per & 4) && z == 0) ghost = row + P * (size_t)d.nz;
+    if ((d.per & 4) && z == d.nz - 1) ghost = row - P * (size_t)d.nz;
     const uint32_t t = d.mask[n] >> kTypeShift;
     if (t == kSolid) {
-      for (int q = 0; q < 38; ++q) g[(size_t)q * d.N + n] = 0.f;
+      for (int q = 0; q < 38; ++q) {
+        row[(size_t)q * d.nx] = 0.f;
+        if (ghost) ghost[(size_t)q * d.nx] = 0.f;
+      }
       continue;
     }
 #pragma unroll
@@ -682,7 +738,9 @@ __global__ void k_init(Dom d, double rho_ref, const double *rho_init, double maj
       const int zs = (int)(src / ((size_t)d.nx * d.ny));
       for (int c = 0; c < 2; ++c) {
         const double r = rho0_of(d.mask, rho_init, maj, mnr, z_front, rres, d.N, src, zs, c);
-        g[(size_t)(c * 19 + k) * d.N + n] = (float)(wd(k) * (r - rho_ref));
+        const float gv = (float)(wd(k) * (r - rho_ref));
+        row[(size_t)(c * 19 + k) * d.nx] = gv;
+        if (ghost) ghost[(size_t)(c * 19 + k) * d.nx] = gv;
       }
     }
   }
@@ -704,7 +762,7 @@ __global__ void k_export(Dom d, Phys P, const double *rres, double *f) {
     const uint32_t m = d.mask[n];
     const uint32_t t = m >> kTypeShift;
     float v[2][19];
-    if (t == kFluid) pull(d, m, (uint32_t)n, x, y, z, v);
+    if (t == kFluid) pull(d, m, x, y, z, v);
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -734,7 +792,7 @@ __global__ void k_density(Dom d, Phys P, const double *rres, double *rho) {
     double r0 = 0.0, r1 = 0.0;
     if (t == kFluid) {
       float v[2][19];
-      pull(d, m, (uint32_t)n, x, y, z, v);
+      pull(d, m, x, y, z, v);
       r0 = (double)(float)((acc_t)P.rho_ref + sum19(v[0]));
       r1 = (double)(float)((acc_t)P.rho_ref + sum19(v[1]));
     } else if (t == kResIn) {
@@ -811,7 +869,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_chunks(const Throat *__r
     const int x = (int)(n % (uint32_t)d.nx), y = (int)((n / (uint32_t)d.nx) % (uint32_t)d.ny);
     const int z = (int)(n / ((uint32_t)d.nx * (uint32_t)d.ny));
     float v[2][19];
-    pull(d, m, n, x, y, z, v);
+    pull(d, m, x, y, z, v);
     const double a = (double)(float)((acc_t)rho_ref + sum19(v[0]));
     const double b = (double)(float)((acc_t)rho_ref + sum19(v[1]));
     acc[0] += a;
@@ -1010,16 +1068,20 @@ __global__ __launch_bounds__(256) void k_copy_requests(const Throat *__restrict_
   const Throat &T = th[c.throat];
   float *g = T.g[parity];
   float *sa = ck[c.throat].stable, *ma = ck[c.throat].main;
-  const size_t N = T.N;
-  for (int q = 0; q < 38; ++q)
-    for (uint32_t i = threadIdx.x; i < c.count; i += blockDim.x) {
-      const size_t o = (size_t)q * N + c.start + i;
-      const float v = g[o];
-      if (req & kSaveStable) sa[o] = v;
-      if (req & kSaveMain) ma[o] = v;
-      if (req & kRestoreStable) g[o] = sa[o];
-      if (req & kRestoreMain) g[o] = ma[o];
-    }
+  // the subdomain's chunks split its whole buffer (ghost planes included)
+  // into equal flat ranges, chunk i taking the i-th
+  const size_t E = pop_elems(T.nx, T.ny, T.nz);
+  const size_t nch = (T.N + kChunkNodes - 1) / kChunkNodes;
+  const size_t len = (E + nch - 1) / nch;
+  const size_t lo = (size_t)(c.start / kChunkNodes) * len;
+  const size_t hi = lo + len < E ? lo + len : E;
+  for (size_t o = lo + threadIdx.x; o < hi; o += blockDim.x) {
+    const float v = g[o];
+    if (req & kSaveStable) sa[o] = v;
+    if (req & kSaveMain) ma[o] = v;
+    if (req & kRestoreStable) g[o] = sa[o];
+    if (req & kRestoreMain) g[o] = ma[o];
+  }
 }
 
 hipError_t launch_ramp_begin(Throat *th, RampDev *rd, const double *pc, const RampCfg &cfg,
