@@ -384,8 +384,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32",
         "storage_dtype": "f32",
+        "sum_dtype": "f64",
         "data": "synthetic (seeded)",
         "config": {"workload": "96^3 single pore throat: 4 spheres, lognormal radii (mean 32 lu, "
                                "sigma 0.15) on a jittered tetrahedron, prism closure, 20-point "
