@@ -300,6 +300,8 @@ def hybrid_leg():
     t0 = time.perf_counter()
     sw, inv, st = network.drain(nw["pore_vol"], nw["throats"], pce, pressures)
     t_net = time.perf_counter() - t0
+    HYB_STATE.update(x=x, r=r, L=L, nw=nw, pressures=pressures, inv=inv, st=st,
+                     wall_s=t_lbm + t_net)
     return {"workload": f"pore network of a {HYB_SPHERES}-sphere dense packing (seed 7, porosity "
                         f"{1 - phi:.2f}): {len(nw['pore_vol'])} pores, {k} throats, {len(idx)} solved "
                         f"by the batched LBM ({SG_RES:g} lu per unit radius, 16-point ramp, cap "
@@ -311,6 +313,53 @@ def hybrid_leg():
             "S_w": [round(float(v), 4) for v in sw],
             "trapped_pores": int((st == network.TRAPPED).sum()),
             "invaded_pores": int((st == network.INVADED).sum())}
+
+
+HYB_STATE = {}
+FULL_CONV = dict(tol=1e-5, check_every=200, max_steps=30000)
+
+
+def full_leg():
+    """The same 40-sphere packing fully resolved (Sec. 3's reference drainage):
+    the slab between a non-wetting bath and a porous membrane in front of the
+    wetting bath, at the resolution of the hybrid's throats, ramped through
+    the hybrid's pressures.  Compared with the hybrid: the slab saturation,
+    and pore by pore the invaded state (the full LBM's saturation within 2 lu
+    of each pore centroid below 1/2, against the network's state)."""
+    from paper_1906_04722_amd import sample_drain
+    from synth import membrane
+    if not HYB_STATE:
+        hybrid_leg()
+    H = HYB_STATE
+    p, info = synth.membrane_sample(H["x"], H["r"], H["L"], res=SG_RES)
+    pcs = H["pressures"] * GAMMA / info["scale"]
+    pts = membrane.lattice_points(H["nw"]["pore_xyz"], info)
+    out = sample_drain.drain_sample(p, pcs, info["slab"], info["membrane_z"], points=pts, log=log,
+                                    **FULL_CONV)
+    Sp = np.array(out["S_points"])
+    seen = np.isfinite(Sp[0])
+    agree = []
+    for i in range(len(pcs)):
+        hyb = (H["st"] == network.INVADED) & (H["inv"] >= 0) & (H["inv"] <= i)
+        full = Sp[i] < 0.5
+        agree.append(float(np.mean(hyb[seen] == full[seen])))
+    return {"workload": f"the hybrid_40 packing fully resolved: {p.nx} x {p.ny} x {p.nz} lattice "
+                        f"({info['scale']:.2f} lu per packing length), periodic in x and y, "
+                        f"non-wetting bath, slab planes {info['slab'][0]}-{info['slab'][1]}, "
+                        f"membrane of single-node holes at z = {info['membrane_z']}, wetting bath; "
+                        f"{len(pcs)} pressures to steady state (|dS| < {FULL_CONV['tol']:g} per "
+                        f"{FULL_CONV['check_every']} steps, cap {FULL_CONV['max_steps']})",
+            "schedule": out["schedule"], "lattice_steps": out["lattice_steps"],
+            "wall_s": round(out["wall_s"], 2), "hybrid_wall_s": round(H["wall_s"], 2),
+            "MLUPS": round(p.n_nodes * out["lattice_steps"] / out["wall_s"] / 1e6, 1),
+            "pressures_per_gamma": [round(float(v), 4) for v in H["pressures"]],
+            "S_slab": [round(v, 4) for v in out["S_slab"]],
+            "S_slab_sharp": [round(v, 4) for v in out["S_slab_sharp"]],
+            "S_behind_membrane_min": round(min(out["S_outlet"]), 4),
+            "converged": [bool(v) for v in out["converged"]],
+            "pores_compared": int(seen.sum()),
+            "pore_state_agreement": [round(v, 4) for v in agree],
+            "pore_state_agreement_mean": round(float(np.mean(agree)), 4)}
 
 
 def dense_512(steps=10):
@@ -343,6 +392,9 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-sample", action="store_true")
     ap.add_argument("--no-hybrid", action="store_true")
+    ap.add_argument("--no-full", action="store_true")
+    ap.add_argument("--full-cap", type=int, default=FULL_CONV["max_steps"],
+                    help="steps per pressure of the fully resolved ramp (full_40)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported "
@@ -409,8 +461,9 @@ def main():
                      "alg_bytes_per_launch": alg_bytes},
     }
     line["copy_probe_GBps"] = round(lbm.bw_probe(4 << 30, 10), 1)
+    FULL_CONV["max_steps"] = a.full_cap
     legs = [("batch", a.no_batch, batch_leg), ("surrogate", a.no_surrogate, surrogate_leg),
-            ("hybrid_40", a.no_hybrid, hybrid_leg),
+            ("hybrid_40", a.no_hybrid, hybrid_leg), ("full_40", a.no_full, full_leg),
             ("dense_512", a.no_dense, dense_512), ("sample_512", a.no_sample, sample_512),
             ("cpu_baseline", a.no_cpu, lambda: cpu_baseline(p))]
     for name, skip, fn in legs:

@@ -15,11 +15,12 @@ from .throats import (tetra_throat, c1_problem, c2_problem, throat_incircle, pc_
 from .packing import (dense_packing, regular_triangulation, interior_facets, packing_throats,
                       packed_sample)
 from .network import pore_network, pore_void_volume
+from .membrane import membrane_sample
 
 __all__ = [
     "Problem", "BC_PERIODIC", "BC_WALLS", "BC_RESERVOIR", "splitmix64", "uniform_pm",
     "layered_density", "flat_interface_density", "droplet_density", "tetra_throat",
     "c1_problem", "c2_problem", "small_throat_problem", "throat_incircle", "pc_ramp", "GAMMA_LAPLACE",
     "dense_packing", "regular_triangulation", "interior_facets", "packing_throats",
-    "packed_sample", "pore_network", "pore_void_volume",
+    "packed_sample", "pore_network", "pore_void_volume", "membrane_sample",
 ]

@@ -45,6 +45,7 @@ def pore_network(x, r, L):
       pore_vol [m]          void volume of each pore (tetrahedra whose centroid
                             lies in the cell),
       pore_z [m]            centroid height,
+      pore_xyz [m][3]       centroid of the tetrahedron's sphere centres,
       throats [k][2]        pore indices; INLET / OUTLET for a throat that opens
                             onto the reservoir above / below the sample,
       facets [k][3][4]      the three throat spheres (centre, radius) as placed
@@ -69,7 +70,8 @@ def pore_network(x, r, L):
         pore_of[key_of(t)] = len(pores)
         pores.append(t)
     pore_vol = np.array([pore_void_volume(P[tets[t]], R[tets[t]]) for t in pores])
-    pore_z = np.array([cen[t][2] for t in pores])
+    pore_xyz = np.array([cen[t] for t in pores]).reshape(-1, 3)
+    pore_z = pore_xyz[:, 2].copy()
 
     def pore_index(t):
         c = cen[t]
@@ -110,7 +112,8 @@ def pore_network(x, r, L):
         facets.append(np.column_stack([P[list(f)], R[list(f)]]))
         v = va if lower_is_a else vb
         apex.append(np.concatenate([P[v], [R[v]]]))
-    return dict(pore_vol=pore_vol, pore_z=pore_z, throats=np.array(throats, dtype=np.int64),
+    return dict(pore_vol=pore_vol, pore_z=pore_z, pore_xyz=pore_xyz,
+                throats=np.array(throats, dtype=np.int64),
                 facets=np.array(facets), apex=np.array(apex))
 
 
