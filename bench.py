@@ -14,6 +14,7 @@ same kernel.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -315,6 +316,42 @@ def hybrid_leg():
             "invaded_pores": int((st == network.INVADED).sum())}
 
 
+THREE_CFG = {"radii": (16.0, 24.0, 32.0)}
+
+
+def three_sphere_leg():
+    """The paper's example throat (three equal touching spheres, prism, no
+    fourth sphere): p_c^e in the paper's normalisation p* = 2 p_c R / gamma
+    at several sphere radii (lattice units), beside the incircle and MS-P
+    estimates, and the p*-V* drainage curve of the largest radius."""
+    from paper_1906_04722_amd import estimators as est
+    rows, curve = [], None
+    for R in THREE_CFG["radii"]:
+        p = synth.three_sphere_throat(R)
+        r_in = est.incircle_radius(R)
+        pcs = synth.pc_ramp(GAMMA, r_in, 20, lo=0.3, hi=1.2)
+        g = lbm.Throat(p)
+        g.autotune(5)
+        t0 = time.perf_counter()
+        out = g.drain(pcs, tol=1e-6, check_every=100, max_steps=40000, bisect_rel=0.005)
+        dt = time.perf_counter() - t0
+        nf = int((g.types() == lbm.LBM_NODE_FLUID).sum())
+        g.close()
+        rows.append({"R": R, "nodes": p.n_nodes, "pce_star": round(est.pc_star(out["pce"], R, GAMMA), 3),
+                     "bracket_star": [round(est.pc_star(out["pce_lo"], R, GAMMA), 3),
+                                      round(est.pc_star(out["pce_hi"], R, GAMMA), 3)],
+                     "wall_s": round(dt, 2), "lattice_steps": int(out["total_steps"])})
+        curve = {"R": R, "p_star": [round(est.pc_star(v, R, GAMMA), 3) for v in pcs],
+                 "V_star": [round(est.v_star(s * nf, R), 4) for s in out["S"]],
+                 "S_w": [round(float(s), 4) for s in out["S"]]}
+    return {"workload": "three equal touching spheres in their prism, no fourth sphere, baths 6 "
+                        "planes beyond the spheres; 20-point ramp from 0.3 to 1.2 x the incircle "
+                        "estimate, bisection to 0.5 %",
+            "incircle_star": round(4.0 / (2.0 / math.sqrt(3.0) - 1.0), 3),
+            "msp_star": round(2.0 / est.msp_radius(1.0), 3),
+            "radii": rows, "curve": curve}
+
+
 HYB_STATE = {}
 FULL_CONV = dict(tol=1e-5, check_every=200, max_steps=30000)
 
@@ -393,6 +430,9 @@ def main():
     ap.add_argument("--no-sample", action="store_true")
     ap.add_argument("--no-hybrid", action="store_true")
     ap.add_argument("--no-full", action="store_true")
+    ap.add_argument("--no-three", action="store_true")
+    ap.add_argument("--three-radii", default=",".join(f"{v:g}" for v in THREE_CFG["radii"]),
+                    help="sphere radii (lattice units) of the three-sphere throat leg")
     ap.add_argument("--full-cap", type=int, default=FULL_CONV["max_steps"],
                     help="steps per pressure of the fully resolved ramp (full_40)")
     a = ap.parse_args()
@@ -462,7 +502,9 @@ def main():
     }
     line["copy_probe_GBps"] = round(lbm.bw_probe(4 << 30, 10), 1)
     FULL_CONV["max_steps"] = a.full_cap
+    THREE_CFG["radii"] = tuple(float(v) for v in a.three_radii.split(","))
     legs = [("batch", a.no_batch, batch_leg), ("surrogate", a.no_surrogate, surrogate_leg),
+            ("three_sphere", a.no_three, three_sphere_leg),
             ("hybrid_40", a.no_hybrid, hybrid_leg), ("full_40", a.no_full, full_leg),
             ("dense_512", a.no_dense, dense_512), ("sample_512", a.no_sample, sample_512),
             ("cpu_baseline", a.no_cpu, lambda: cpu_baseline(p))]

@@ -89,6 +89,28 @@ def small_throat_problem(n=24, seed=7, amp=1e-3, rho_in=2.05, gap=2.0):
 
 
 
+def three_sphere_throat(R=32.0, margin=6, seed=3, amp=1e-3, rho_in=2.0):
+    """The paper's example throat (Sec. 2.2.2): three equal spheres of radius
+    R (lattice units) in mutual contact, centres on one plane normal to z, the
+    prism over their triangle as the closure, and no fourth sphere.  The
+    non-wetting bath is at z = 0 and the wetting one at z = nz - 1, `margin`
+    open planes beyond the spheres on each side.  The invasion probe sits on
+    the prism axis 3 lu past the plane of the centres."""
+    x0 = y0 = 1.0
+    h = math.sqrt(3.0) * R
+    nx = int(math.ceil(x0 + 2.0 * R)) + 2
+    ny = int(math.ceil(y0 + h)) + 2
+    zt = margin + int(math.ceil(R)) + 1
+    nz = zt + int(math.ceil(R)) + margin + 2
+    sph = np.array([[x0, y0, zt, R], [x0 + 2.0 * R, y0, zt, R], [x0 + R, y0 + h, zt, R]])
+    axis = (x0 + R, y0 + h / 3.0)
+    p = Problem(nx=nx, ny=ny, nz=nz, bc=(BC_WALLS, BC_WALLS, BC_RESERVOIR), spheres=sph,
+                prism_ids=(0, 1, 2), rho_in_nw=rho_in, rho_out_w=2.0, z_front=margin,
+                probe=_probe_near((axis[0], axis[1], zt + 3)))
+    p.rho_init = layered_density(nx, ny, nz, p.z_front, p.rho_major, p.rho_minor, seed, amp)
+    return p
+
+
 def throat_incircle(spheres, ids=(0, 1, 2)):
     """Radius and centre of the circle in the xy-plane tangent to the three
     throat circles (sphere cross-sections through their centres): the
