@@ -213,6 +213,27 @@ def surrogate_leg():
                       "final_within_1pct": round(float((fin <= 0.01).mean()), 4),
                       "network_err_median_where_answered":
                           round(float(np.median(err_raw[take])), 4) if take.any() else None})
+    # the calibrated no-LBM estimate of the paper's cheap methods: MS-P on the
+    # throat's cross-section, scaled by its median LBM/MS-P ratio on the
+    # training throats
+    from paper_1906_04722_amd import estimators as est
+
+    def msp_pc(probs):
+        out = []
+        for p in probs:
+            S = np.asarray(p.spheres)[list(p.prism_ids)]
+            out.append(GAMMA / est.msp_general_radius([(s[0], s[1], s[3]) for s in S]))
+        return np.array(out)
+
+    t0 = time.perf_counter()
+    msp_te = msp_pc(te)
+    t_msp = time.perf_counter() - t0
+    pce_tr = np.array([d["pce"] for d in drains])
+    msp_tr = msp_pc(tr)
+    fin = np.isfinite(pce_tr) & np.isfinite(msp_tr)
+    k_msp = float(np.median(pce_tr[fin] / msp_tr[fin]))
+    ok_m = ok & np.isfinite(msp_te)
+    err_msp = np.abs(k_msp * msp_te[ok_m] - pref[ok_m]) / pref[ok_m]
     # inference alone on many descriptor rows (the held-out rows repeated)
     rows = np.tile(Fte, (SG_INFER // len(Fte) + 1, 1))[:SG_INFER]
     m.predict(rows[:4096])
@@ -233,6 +254,10 @@ def surrogate_leg():
             "pce_within_1pct": round(float((err <= 0.01).mean()), 4),
             "accepted_err_median": round(float(np.median(err_acc)), 4) if acc.any() else None,
             "baseline_mean_err_median": round(float(np.median(base)), 4),
+            "msp_lbm_ratio_train_median": round(k_msp, 4),
+            "msp_calibrated_err_median": round(float(np.median(err_msp)), 4),
+            "msp_calibrated_within_5pct": round(float((err_msp <= 0.05).mean()), 4),
+            "msp_throats_per_s_host": round(len(te) / t_msp, 1),
             "network_err_median": round(float(np.median(err_raw)), 4),
             "network_within_5pct": round(float((err_raw <= 0.05).mean()), 4),
             "tradeoff": trade,
