@@ -66,7 +66,12 @@ def test_invalid_arguments_rejected_without_gpu_work():
     P.tau[0] = 1.0
     P.nx = 2
     assert L.lbm_throat_init(ctypes.byref(P), ctypes.byref(h)) == lbm.LBM_EINVAL
-    P.nx = 40
+    # the three-plane pull offsets of the row-interleaved storage are 32-bit:
+    # at most 9,418,786 nodes per z-plane (here 4000 x 3000 x 3 nodes)
+    P.nx, P.ny, P.nz = 4000, 3000, 3
+    assert L.lbm_throat_init(ctypes.byref(P), ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert b"plane" in L.lbm_last_error()
+    P.nx, P.ny, P.nz = 40, 40, 40
     P.bc[0] = lbm.LBM_BC_RESERVOIR
     assert L.lbm_throat_init(ctypes.byref(P), ctypes.byref(h)) == lbm.LBM_EINVAL
     assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
