@@ -54,7 +54,8 @@ extern "C" {
 #define LBM_EHIP (-3)       /* a HIP runtime call failed                    */
 #define LBM_ENONFINITE (-4) /* the state became non-finite                  */
 #define LBM_ESTATE (-5)     /* call not valid in the handle's state         */
-#define LBM_WNOTCONV 1      /* a ramp point hit its step cap                */
+#define LBM_WNOTCONV 1      /* a ramp point hit its step cap, or bisection
+                               its run limit                                */
 #define LBM_WPARTIAL 2      /* batch: some subdomains failed (see status)  */
 
 /* boundary kinds, one per axis */
@@ -179,8 +180,10 @@ int lbm_probe_invaded(lbm_throat_t h, int *invaded);
  * first invaded point, bisect between the last stable state and pc[i] on a
  * copy of the state until the bracket is within c->bisect_rel; the entry
  * pressure is reported as that bracket (Sec. 2.2.2: p_c^e is the maximum p_c
- * reached before invasion).  Synchronous.  Returns LBM_WNOTCONV if a point
- * hit its cap. */
+ * reached before invasion).  Bisection stops after 40 runs: a throat
+ * already invaded at pc[0] brackets from 0, where the relative width may
+ * never shrink; its bracket is then reported as reached.  Synchronous.
+ * Returns LBM_WNOTCONV if a point hit its cap or bisection its run limit. */
 int lbm_drain_throat(lbm_throat_t h, const double *pc, int n_pc, const lbm_conv *c,
                      lbm_drain_result *out);
 

@@ -646,7 +646,9 @@ int orc_drain(orc_sim *s, const double *pc, int n_pc, double tol, int every, lon
       orc_free(stable);
       return -2;
     }
-    while ((hi - lo) / hi > bisect_rel) {
+    /* at most 40 runs: from a lower bracket of 0 (invaded at pc[0]) halving
+       alone need not reach the relative width */
+    for (int runs = 0; (hi - lo) / hi > bisect_rel && runs < 40; ++runs) {
       double mid = 0.5 * (lo + hi);
       double Sm;
       long long nm;

@@ -770,7 +770,13 @@ int lbm_drain_throat(lbm_throat_t h, const double *pc, int n_pc, const lbm_conv 
     // bisect on copies of the last stable state; the ramp state is kept aside
     const double main_rho_in = h->rho_in;
     TRY(copy_state(h, mainsave, h->g[h->cur]));
+    int runs = 0;
     while ((hi - lo) / hi > c->bisect_rel) {
+      if (runs == sc::kMaxBisect) {  // bracket left wider than asked (see kMaxBisect)
+        warn = true;
+        break;
+      }
+      ++runs;
       const double mid = 0.5 * (lo + hi);
       TRY(copy_state(h, h->g[h->cur], stable));
       TRY(set_rho_in(h, lbm_rho_in_for_pc(h, mid)));

@@ -299,7 +299,7 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
   if (int r = capture_chunk(B, cfg)) return r;
   // replay until every subdomain has finished its ramp; a bound on the
   // replays guards against a run that would never end
-  long long max_bisect = 64;
+  const long long max_bisect = sc::kMaxBisect;
   const long long max_replays =
       (long long)(n_pc + max_bisect + 2) * ((c->max_steps + c->check_every - 1) / c->check_every) +
       16;

@@ -157,6 +157,11 @@ enum : int { kPhaseRamp = 0, kPhaseBisect = 1, kPhaseDone = 2 };
 // copy requests executed after each ramp decision, saves before restores
 enum : int { kSaveStable = 1, kSaveMain = 2, kRestoreStable = 4, kRestoreMain = 8 };
 
+// bisection runs of one drain at most: a throat already invaded at the first
+// ramp point has 0 as its lower bracket, where halving alone need not reach
+// the relative width; the drain then ends with its bracket and a warning
+constexpr int kMaxBisect = 40;
+
 struct RampCfg {
   double tol;        // |S(t) - S(t - every)| < tol ends a ramp point
   double rel;        // bisection stops at (hi - lo) / hi <= rel

@@ -1036,9 +1036,11 @@ __global__ __launch_bounds__(256) void k_ramp_advance(Throat *th, RampDev *rd, c
           R.req |= kSaveStable;
           R.S_stable = S;
         }
-        if ((R.hi - R.lo) / R.hi > cfg.rel) {
+        const bool wide = (R.hi - R.lo) / R.hi > cfg.rel;
+        if (wide && R.n_bisect < kMaxBisect) {
           ramp_trial(T, R);
         } else {
+          R.warn |= wide;
           R.req |= kRestoreMain;
           R.phase = kPhaseRamp;
           ramp_next_point(T, R, pcs, cfg, R.S_main);
