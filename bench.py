@@ -491,7 +491,7 @@ def main():
     out = results[-1][0]
 
     line = {
-        "metric": "MLUPS (Shan-Chen two-component D3Q19, 96^3 throat drainage ramp)",
+        "metric": "MLUPS + % HBM roofline (Shan-Chen FP32); throats/sec to p_c^e at \u22641% err",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
