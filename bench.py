@@ -296,17 +296,18 @@ def sample_512():
             "S_w": [round(float(x), 5) for x in out["S"]]}
 
 
-def hybrid_leg():
-    """Hybrid drainage of a 40-sphere packing: throat entry pressures from one
+def _hybrid(x, r, L, res, state, name):
+    """Hybrid drainage of a periodic packing: throat entry pressures from one
     lbm_drain_batch call, assembled by lbm_network_drain.  Facets whose
     opening lies outside their triangle of centres have no prism subdomain;
     they get the incircle estimate scaled by the median LBM/incircle ratio of
     the solved throats.  Entry pressures are compared in units of the
-    interfacial tension per packing length (p_c^e * lu-per-unit / gamma)."""
+    interfacial tension per packing length (p_c^e * lu-per-unit / gamma).
+    `res`: lattice units per packing length; `state` receives what the fully
+    resolved comparison needs."""
     from synth import network as net_geo
-    x, r, L, phi, _ = synth.dense_packing(HYB_SPHERES, seed=7)
     nw = net_geo.pore_network(x, r, L)
-    probs, r_lu, scale, r_unit = net_geo.throat_problems(nw, res=SG_RES, side_range=SG_SIDES)
+    probs, r_lu, scale, r_unit = net_geo.throat_problems(nw, res=res, side_range=SG_SIDES)
     idx = [i for i, p in enumerate(probs) if p is not None]
     pcs = np.array([synth.pc_ramp(GAMMA, r_lu[i], 16) for i in idx])
     t0 = time.perf_counter()
@@ -326,12 +327,12 @@ def hybrid_leg():
     t0 = time.perf_counter()
     sw, inv, st = network.drain(nw["pore_vol"], nw["throats"], pce, pressures)
     t_net = time.perf_counter() - t0
-    HYB_STATE.update(x=x, r=r, L=L, nw=nw, pressures=pressures, inv=inv, st=st,
-                     wall_s=t_lbm + t_net)
-    return {"workload": f"pore network of a {HYB_SPHERES}-sphere dense packing (seed 7, porosity "
-                        f"{1 - phi:.2f}): {len(nw['pore_vol'])} pores, {k} throats, {len(idx)} solved "
-                        f"by the batched LBM ({SG_RES:g} lu per unit radius, 16-point ramp, cap "
-                        f"{HYB_CONV['max_steps']}), the rest by the scaled incircle estimate",
+    state.update(x=x, r=r, L=L, res=res, nw=nw, pressures=pressures, inv=inv, st=st,
+                 wall_s=t_lbm + t_net, name=name)
+    return {"workload": f"pore network of {name}: {len(nw['pore_vol'])} pores, {k} throats, "
+                        f"{len(idx)} solved by the batched LBM ({res:.3g} lu per packing length, "
+                        f"16-point ramp, cap {HYB_CONV['max_steps']}), the rest by the scaled "
+                        "incircle estimate",
             "throat_lbm_s": round(t_lbm, 2), "throats_per_s": round(len(idx) / t_lbm, 2),
             "lbm_fluid_MLUPS": round(info["fluid_updates"] / (info["wall_ms"] * 1e3), 1),
             "network_ms": round(t_net * 1e3, 3), "lbm_over_incircle_median": round(ratio, 4),
@@ -339,6 +340,14 @@ def hybrid_leg():
             "S_w": [round(float(v), 4) for v in sw],
             "trapped_pores": int((st == network.TRAPPED).sum()),
             "invaded_pores": int((st == network.INVADED).sum())}
+
+
+def hybrid_leg():
+    """The hybrid method on a 40-sphere dense packing (mean radius 1, porosity
+    0.38) at 12 lu per unit radius."""
+    x, r, L, phi, _ = synth.dense_packing(HYB_SPHERES, seed=7)
+    return _hybrid(x, r, L, SG_RES, HYB_STATE,
+                   f"a {HYB_SPHERES}-sphere dense packing (seed 7, porosity {1 - phi:.2f})")
 
 
 THREE_CFG = {"radii": (16.0, 24.0, 32.0)}
@@ -381,19 +390,16 @@ HYB_STATE = {}
 FULL_CONV = dict(tol=1e-5, check_every=200, max_steps=30000)
 
 
-def full_leg():
-    """The same 40-sphere packing fully resolved (Sec. 3's reference drainage):
-    the slab between a non-wetting bath and a porous membrane in front of the
-    wetting bath, at the resolution of the hybrid's throats, ramped through
-    the hybrid's pressures.  Compared with the hybrid: the slab saturation,
-    and pore by pore the invaded state (the full LBM's saturation within 2 lu
-    of each pore centroid below 1/2, against the network's state)."""
+def _full(H):
+    """The packing of a hybrid run fully resolved (Sec. 3's reference
+    drainage): the slab between a non-wetting bath and a porous membrane in
+    front of the wetting bath, at the resolution of the hybrid's throats,
+    ramped through the hybrid's pressures.  Compared with the hybrid: the slab
+    saturation, and pore by pore the invaded state (the full LBM's saturation
+    within 2 lu of each pore centroid below 1/2, against the network's state)."""
     from paper_1906_04722_amd import sample_drain
     from synth import membrane
-    if not HYB_STATE:
-        hybrid_leg()
-    H = HYB_STATE
-    p, info = synth.membrane_sample(H["x"], H["r"], H["L"], res=SG_RES)
+    p, info = synth.membrane_sample(H["x"], H["r"], H["L"], res=H["res"])
     pcs = H["pressures"] * GAMMA / info["scale"]
     pts = membrane.lattice_points(H["nw"]["pore_xyz"], info)
     out = sample_drain.drain_sample(p, pcs, info["slab"], info["membrane_z"], points=pts, log=log,
@@ -405,8 +411,8 @@ def full_leg():
         hyb = (H["st"] == network.INVADED) & (H["inv"] >= 0) & (H["inv"] <= i)
         full = Sp[i] < 0.5
         agree.append(float(np.mean(hyb[seen] == full[seen])))
-    return {"workload": f"the hybrid_40 packing fully resolved: {p.nx} x {p.ny} x {p.nz} lattice "
-                        f"({info['scale']:.2f} lu per packing length), periodic in x and y, "
+    return {"workload": f"{H['name']} fully resolved: {p.nx} x {p.ny} x {p.nz} lattice "
+                        f"({info['scale']:.3g} lu per packing length), periodic in x and y, "
                         f"non-wetting bath, slab planes {info['slab'][0]}-{info['slab'][1]}, "
                         f"membrane of single-node holes at z = {info['membrane_z']}, wetting bath; "
                         f"{len(pcs)} pressures to steady state (|dS| < {FULL_CONV['tol']:g} per "
@@ -422,6 +428,28 @@ def full_leg():
             "pores_compared": int(seen.sum()),
             "pore_state_agreement": [round(v, 4) for v in agree],
             "pore_state_agreement_mean": round(float(np.mean(agree)), 4)}
+
+
+def full_leg():
+    """The hybrid_40 packing fully resolved, compared with the hybrid."""
+    if not HYB_STATE:
+        hybrid_leg()
+    return _full(HYB_STATE)
+
+
+PAPER40_STATE = {}
+
+
+def paper40_leg():
+    """A replica of the paper's sample sizes (Sec. 3: 40 polydisperse spheres
+    of mean radius 1.26 in a 10-unit cube; log-sd 0.2 assumed, solid fraction
+    0.40 follows), periodic like the network: the hybrid and the fully
+    resolved drainage at 12 lu per mean radius, compared."""
+    x, r, L, phi, _ = synth.dense_packing(40, mean_r=1.26, seed=7, side=10.0)
+    hyb = _hybrid(x, r, L, SG_RES / 1.26, PAPER40_STATE,
+                  f"a 40-sphere packing in a 10-unit cell (mean radius 1.26, seed 7, solid "
+                  f"fraction {phi:.2f})")
+    return {"hybrid": hyb, "full": _full(PAPER40_STATE)}
 
 
 def dense_512(steps=10):
@@ -456,6 +484,8 @@ def main():
     ap.add_argument("--no-hybrid", action="store_true")
     ap.add_argument("--no-full", action="store_true")
     ap.add_argument("--no-three", action="store_true")
+    ap.add_argument("--paper40", action="store_true",
+                    help="also run the replica of the paper's 40-sphere sample (about 2 min)")
     ap.add_argument("--three-radii", default=",".join(f"{v:g}" for v in THREE_CFG["radii"]),
                     help="sphere radii (lattice units) of the three-sphere throat leg")
     ap.add_argument("--full-cap", type=int, default=FULL_CONV["max_steps"],
@@ -531,6 +561,7 @@ def main():
     legs = [("batch", a.no_batch, batch_leg), ("surrogate", a.no_surrogate, surrogate_leg),
             ("three_sphere", a.no_three, three_sphere_leg),
             ("hybrid_40", a.no_hybrid, hybrid_leg), ("full_40", a.no_full, full_leg),
+            ("paper_40", not a.paper40, paper40_leg),
             ("dense_512", a.no_dense, dense_512), ("sample_512", a.no_sample, sample_512),
             ("cpu_baseline", a.no_cpu, lambda: cpu_baseline(p))]
     for name, skip, fn in legs:

@@ -24,15 +24,16 @@ from .throats import _normals, throat_incircle
 
 
 def dense_packing(n=500, mean_r=1.0, sigma=0.2, solid_fraction=0.62, seed=3, tol=1e-4,
-                  max_iter=20000):
+                  max_iter=20000, side=None):
     """n spheres with lognormal radii (arithmetic mean mean_r, log-sd sigma)
     relaxed to no overlap in a periodic cube whose side gives the requested
-    solid fraction.  Returns (centres [n][3], radii [n], box side, achieved
+    solid fraction (or of the given side, the solid fraction then following
+    from the radii).  Returns (centres [n][3], radii [n], box side, achieved
     solid fraction, largest remaining overlap / mean radius)."""
     z = _normals(seed, n)
     r = np.exp(math.log(mean_r) - 0.5 * sigma * sigma + sigma * z)
     vol = (4.0 / 3.0) * math.pi * (r ** 3).sum()
-    L = (vol / solid_fraction) ** (1.0 / 3.0)
+    L = float(side) if side is not None else (vol / solid_fraction) ** (1.0 / 3.0)
     x = uniform01(seed + 77, 3 * n).reshape(n, 3) * L
     rmax = r.max()
     worst = np.inf
