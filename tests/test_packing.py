@@ -109,3 +109,16 @@ def test_throat_boxes():
         px, py, pz = p.probe
         assert t[pz, py, px] == 0
         assert (t == 0).mean() > 0.05
+
+
+def test_packing_of_a_given_cell_side():
+    # the paper's sample sizes: 40 spheres of mean radius 1.26 in a 10-unit
+    # cell; the solid fraction then follows from the drawn radii
+    x, r, L, phi, worst = packing.dense_packing(40, mean_r=1.26, seed=7, side=10.0)
+    assert L == 10.0
+    assert abs(phi - (4.0 / 3.0) * np.pi * (r ** 3).sum() / 1000.0) < 1e-12
+    assert worst < 1e-4
+    d = x[:, None, :] - x[None, :, :]
+    d -= L * np.round(d / L)
+    dist = np.sqrt((d ** 2).sum(-1)) + np.eye(len(r)) * 1e9
+    assert ((r[:, None] + r[None, :] - dist) / r.mean()).max() < 1e-4
