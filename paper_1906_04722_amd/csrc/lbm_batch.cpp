@@ -280,6 +280,10 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
     std::vector<int> zper;
     for (int t = 0; t < n; ++t)
       if (B.h[t]->per & 4) zper.push_back(t);
+    if (zper.size() > 65535) {  // the ghost-plane kernel's grid y holds them
+      set_err("lbm_drain_batch: at most 65535 z-periodic subdomains per batch");
+      return LBM_EINVAL;
+    }
     B.n_zper = (int)zper.size();
     if (dalloc(&B.zper_d, zper.size())) return LBM_ENOMEM;
     if (!zper.empty())
