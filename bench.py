@@ -43,7 +43,8 @@ BATCH_N_PC = 16
 BATCH_CONV = dict(tol=1e-6, check_every=100, max_steps=4000, bisect_rel=0.01)
 # learned surrogate: trained on throats of one packing drained by the batched
 # LBM, evaluated on throats of another packing against the plain LBM
-SG_TRAIN, SG_TEST, SG_INFER = 512, 256, 100000
+SG_TEST, SG_INFER = 256, 100000
+SG_CFG = {"train": 512}
 SG_RES, SG_SIDES = 12.0, (24, 64)
 SG_CONV = dict(tol=1e-6, check_every=100, max_steps=1500, bisect_rel=0.01)
 SG_FIT = dict(epochs=200, batch=64, lr=1e-3, seed=2)
@@ -166,14 +167,20 @@ def surrogate_leg():
     """Train the ensemble on LBM-drained throats, then answer held-out throats
     with surrogate + LBM fallback and compare with the plain batched LBM."""
     def throats(seed, n):
+        # the 600-sphere packing holds about 6100 usable throats
         probs, rins, _ = synth.packing_throats(n_throats=n, seed=seed, res=SG_RES,
                                                side_range=SG_SIDES, amp=0)
         return probs, np.array([synth.pc_ramp(GAMMA, r, 16) for r in rins])
 
-    tr, tr_pc = throats(5, SG_TRAIN)
+    n_train = SG_CFG["train"]
+    tr, tr_pc = throats(5, n_train)
     te, te_pc = throats(6, SG_TEST)
     t0 = time.perf_counter()
-    drains, _ = lbm.drain_batch(tr, tr_pc, **SG_CONV)
+    drains = []
+    for c0 in range(0, len(tr), 1024):  # batches of 1024 throats, each filling the GPU
+        d, _ = lbm.drain_batch(tr[c0:c0 + 1024], tr_pc[c0:c0 + 1024], **SG_CONV)
+        drains += d
+        log(f"surrogate: {len(drains)} of {len(tr)} training throats drained")
     t_data = time.perf_counter() - t0
     log(f"surrogate: training set drained ({len(tr)} throats, {t_data:.1f} s)")
     F, T, _ = surrogate.training_set(tr, drains)
@@ -484,6 +491,8 @@ def main():
     ap.add_argument("--no-hybrid", action="store_true")
     ap.add_argument("--no-full", action="store_true")
     ap.add_argument("--no-three", action="store_true")
+    ap.add_argument("--sg-train", type=int, default=SG_CFG["train"],
+                    help="throats drained to train the surrogate (default 512, at most ~6000)")
     ap.add_argument("--paper40", action="store_true",
                     help="also run the replica of the paper's 40-sphere sample (about 2 min)")
     ap.add_argument("--three-radii", default=",".join(f"{v:g}" for v in THREE_CFG["radii"]),
@@ -557,6 +566,7 @@ def main():
     }
     line["copy_probe_GBps"] = round(lbm.bw_probe(4 << 30, 10), 1)
     FULL_CONV["max_steps"] = a.full_cap
+    SG_CFG["train"] = a.sg_train
     THREE_CFG["radii"] = tuple(float(v) for v in a.three_radii.split(","))
     legs = [("batch", a.no_batch, batch_leg), ("surrogate", a.no_surrogate, surrogate_leg),
             ("three_sphere", a.no_three, three_sphere_leg),
