@@ -320,6 +320,14 @@ def _hybrid(x, r, L, res, state, name):
     t0 = time.perf_counter()
     drains, info = lbm.drain_batch([probs[i] for i in idx], pcs, **HYB_CONV)
     t_lbm = time.perf_counter() - t0
+    # the same kind of throat drained one at a time (8 of them), for the
+    # batching gain on subdomains too small to fill the GPU
+    t0 = time.perf_counter()
+    for i, pc in zip(idx[:8], pcs[:8]):
+        g = lbm.Throat(probs[i])
+        g.drain(pc, **HYB_CONV)
+        g.close()
+    t_one = (time.perf_counter() - t0) / 8
     k = len(probs)
     pce = np.full(k, np.nan)
     for i, d in zip(idx, drains):
@@ -341,6 +349,7 @@ def _hybrid(x, r, L, res, state, name):
                         f"16-point ramp, cap {HYB_CONV['max_steps']}), the rest by the scaled "
                         "incircle estimate",
             "throat_lbm_s": round(t_lbm, 2), "throats_per_s": round(len(idx) / t_lbm, 2),
+            "throats_per_s_one_at_a_time": round(1.0 / t_one, 3),
             "lbm_fluid_MLUPS": round(info["fluid_updates"] / (info["wall_ms"] * 1e3), 1),
             "network_ms": round(t_net * 1e3, 3), "lbm_over_incircle_median": round(ratio, 4),
             "pressures_per_gamma": [round(float(v), 4) for v in pressures],
