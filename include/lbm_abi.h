@@ -82,7 +82,8 @@ typedef struct {
 /* Statement of one subdomain run (Sec. 2.1 and 2.2). */
 typedef struct {
   int nx, ny, nz;            /* box size in nodes, each >= 3, product < 2^29,
-                                nx * ny <= 9,418,786 (3-plane pull offsets)  */
+                                nx, ny rounded up to multiples of 8 and 4:
+                                product <= 9,418,786 (3-plane pull offsets)  */
   int bc[3];                 /* LBM_BC_* for x, y, z (RESERVOIR only for z)   */
   int n_spheres;             /* >= 0                                          */
   const lbm_sphere *spheres; /* [n_spheres], host                             */

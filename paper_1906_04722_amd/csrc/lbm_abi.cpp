@@ -172,9 +172,9 @@ int validate(const lbm_params *p) {
             (long long)p->nx * p->ny * p->nz);
     return LBM_EINVAL;
   }
-  if ((long long)p->nx * p->ny > sc::kMaxPlaneNodes) {
-    set_err("plane of %lld nodes: at most %lld nodes per z-plane",
-            (long long)p->nx * p->ny, sc::kMaxPlaneNodes);
+  if ((long long)sc::pad_x(p->nx) * sc::pad_y(p->ny) > sc::kMaxPlaneNodes) {
+    set_err("plane of %lld nodes (padded to %d x %d): at most %lld nodes per z-plane",
+            (long long)p->nx * p->ny, sc::pad_x(p->nx), sc::pad_y(p->ny), sc::kMaxPlaneNodes);
     return LBM_EINVAL;
   }
   for (int a = 0; a < 3; ++a) {
@@ -567,8 +567,17 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
     std::vector<uint32_t> list;
     list.reserve((size_t)(h->N - (size_t)std::count(h->types.begin(), h->types.end(),
                                                      (uint8_t)sc::kSolid)));
-    for (size_t n = 0; n < h->N; ++n)
-      if (h->types[n] != sc::kSolid) list.push_back((uint32_t)n);
+    // in storage order (brick by brick), so that the lanes of a wavefront
+    // read and write whole lines of the population buffers
+    const size_t nxy = (size_t)h->nx * h->ny;
+    for (int z = 0; z < h->nz; ++z)
+      for (int by = 0; by < h->ny; by += sc::kBY)
+        for (int bx = 0; bx < h->nx; bx += sc::kBX)
+          for (int y = by; y < std::min(by + sc::kBY, h->ny); ++y)
+            for (int x = bx; x < std::min(bx + sc::kBX, h->nx); ++x) {
+              const size_t n = (size_t)z * nxy + (size_t)y * h->nx + x;
+              if (h->types[n] != sc::kSolid) list.push_back((uint32_t)n);
+            }
     h->nlist = (uint32_t)list.size();
     ALLOC(h->list_d, sizeof(uint32_t) * std::max<size_t>(list.size(), 1));
     ALLOC(h->rho_d, sizeof(float2) * h->N);

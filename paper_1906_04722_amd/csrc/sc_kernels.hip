@@ -74,10 +74,13 @@ __device__ __forceinline__ int wrap(int c, int n) { return c < 0 ? c + n : (c >=
 // at (X, Y, Z) with link bits m: g_k from x - e_k, or the reflected g_opp(k)
 // at x itself when the link to x - e_k is cut by a solid node or a wall
 // (half-way bounce-back).  Addresses are the start of plane Z - 1 (uniform
-// across a tile) plus a 32-bit byte offset per lane; with P the elements of
-// a plane and R = 38 nx those of a row, population q of the node itself is at
-// element P + Y R + q nx + X, of the source node at (1 - ez) P + Ys R + q nx
-// + Xs.  The second component's populations follow 19 rows of nx later.
+// across a tile) plus a 32-bit byte offset per lane.  In the brick storage
+// the offset of a node is the sum of an x part and a y part (brick_x,
+// brick_y); with P the elements of a plane, population q of the node itself
+// is at P + y(Y) + x(X) + 32 q, of the source node at (1 - ez) P + y(Ys) +
+// x(Xs) + 32 q.  The second component's populations follow 19 * 32 later.
+// Xs and Ys are taken modulo nx and ny: across a periodic face that is the
+// wrapped neighbour, across a wall the link is cut and the offset unused.
 // global-memory views of the population buffers: loads and stores then take
 // a uniform 64-bit base and a 32-bit per-lane offset
 typedef const __attribute__((address_space(1))) char gcchar;
@@ -85,52 +88,52 @@ typedef __attribute__((address_space(1))) char gchar;
 
 template <int K>
 __device__ __forceinline__ void pull_dir(gcchar *b0, gcchar *b1, uint32_t m, uint32_t own,
-                                         uint32_t s, uint32_t nx, float (&v)[2][19]) {
+                                         uint32_t s, float (&v)[2][19]) {
   constexpr int o = opp(K);
   const bool cut = (m >> K) & 1u;
-  const uint32_t off = cut ? own + (uint32_t)o * nx : s + (uint32_t)K * nx;
+  const uint32_t off = cut ? own + (uint32_t)(o * kBN) : s + (uint32_t)(K * kBN);
   v[0][K] = *(const __attribute__((address_space(1))) float *)(b0 + (size_t)(off * 4u));
   v[1][K] = *(const __attribute__((address_space(1))) float *)(b1 + (size_t)(off * 4u));
 }
 
+// source offset of direction K: planes, then the y and x parts of x - e_k
+// (index 0: coordinate - 1, 1: itself, 2: + 1)
 template <int K>
-__device__ __forceinline__ uint32_t src_index(uint32_t own, uint32_t R, uint32_t P, uint32_t cxm,
-                                              uint32_t cxp, uint32_t cym, uint32_t cyp) {
-  // x - e_k in modular 32-bit arithmetic; the c?? terms wrap across a
-  // periodic x or y face (on other faces the link is cut and the value is
-  // unused); z needs no wrap thanks to the ghost planes
-  uint32_t s = own;
-  if (ex(K) > 0) s = s - 1u + cxm;
-  if (ex(K) < 0) s = s + 1u - cxp;
-  if (ey(K) > 0) s = s - R + cym;
-  if (ey(K) < 0) s = s + R - cyp;
-  if (ez(K) > 0) s = s - P;
-  if (ez(K) < 0) s = s + P;
-  return s;
+__device__ __forceinline__ uint32_t src_index(uint32_t P, const uint32_t (&py)[3],
+                                              const uint32_t (&px)[3]) {
+  return (uint32_t)(1 - ez(K)) * P + py[1 - ey(K)] + px[1 - ex(K)];
 }
 
 template <int K>
 __device__ __forceinline__ void pull_rec(gcchar *b0, gcchar *b1, uint32_t m, uint32_t own,
-                                         uint32_t nx, uint32_t R, uint32_t P, uint32_t cxm,
-                                         uint32_t cxp, uint32_t cym, uint32_t cyp,
-                                         float (&v)[2][19]) {
-  pull_dir<K>(b0, b1, m, own, src_index<K>(own, R, P, cxm, cxp, cym, cyp), nx, v);
-  if constexpr (K + 1 < 19) pull_rec<K + 1>(b0, b1, m, own, nx, R, P, cxm, cxp, cym, cyp, v);
+                                         uint32_t P, const uint32_t (&py)[3],
+                                         const uint32_t (&px)[3], float (&v)[2][19]) {
+  pull_dir<K>(b0, b1, m, own, src_index<K>(P, py, px), v);
+  if constexpr (K + 1 < 19) pull_rec<K + 1>(b0, b1, m, own, P, py, px, v);
 }
 
 __device__ __forceinline__ void pull(const Dom &d, uint32_t m, int X, int Y, int Z,
                                      float (&v)[2][19]) {
-  const uint32_t nx = (uint32_t)d.nx, R = 38u * nx, P = R * (uint32_t)d.ny;
+  const uint32_t P = (uint32_t)pop_plane(d.nx, d.ny);
   gcchar *b0 = (gcchar *)(d.src + (size_t)P * (size_t)Z);
-  gcchar *b1 = b0 + (size_t)19 * nx * 4;
-  uint32_t own = P + (uint32_t)Y * R + (uint32_t)X;
+  gcchar *b1 = b0 + (size_t)(19 * kBN * 4);
+  uint32_t px[3], py[3];
+  px[0] = brick_x(X == 0 ? d.nx - 1 : X - 1);
+  px[1] = brick_x(X);
+  px[2] = brick_x(X == d.nx - 1 ? 0 : X + 1);
+  py[0] = brick_y(Y == 0 ? d.ny - 1 : Y - 1, d.nx);
+  py[1] = brick_y(Y, d.nx);
+  py[2] = brick_y(Y == d.ny - 1 ? 0 : Y + 1, d.nx);
   // The offsets do not depend on Z (the base does), so a z-marching loop
   // would otherwise keep all 38 of them live in registers across planes;
-  // this opaque move makes them cheap per-plane arithmetic instead.
-  asm volatile("" : "+v"(own));
-  const uint32_t cxm = X == 0 ? nx : 0u, cxp = X == d.nx - 1 ? nx : 0u;
-  const uint32_t cym = Y == 0 ? P : 0u, cyp = Y == d.ny - 1 ? P : 0u;
-  pull_rec<0>(b0, b1, m, own, nx, R, P, cxm, cxp, cym, cyp, v);
+  // these opaque moves make them cheap per-plane arithmetic instead.
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    asm volatile("" : "+v"(px[i]));
+    asm volatile("" : "+v"(py[i]));
+  }
+  const uint32_t own = P + py[1] + px[1];
+  pull_rec<0>(b0, b1, m, own, P, py, px, v);
 }
 
 // Type of the density sums.  Populations are stored in FP32 (the HBM
@@ -254,24 +257,19 @@ __device__ __forceinline__ void collide(const Phys &P, uint32_t m, const float (
 
 // Store the post-collision populations of the node at (X, Y, Z) (the ghost
 // planes of z-periodic subdomains are refreshed by k_ghost after the step).
-__device__ __forceinline__ void store_plane(float *plane, uint32_t own, uint32_t nx,
-                                            const float (&v)[2][19]) {
-  gchar *b = (gchar *)plane;
+__device__ __forceinline__ void store_node(const Dom &d, int X, int Y, int Z,
+                                           const float (&v)[2][19]) {
+  const size_t P = pop_plane(d.nx, d.ny);
+  uint32_t own = brick_y(Y, d.nx) + brick_x(X);
+  asm volatile("" : "+v"(own));  // per-plane offsets, as in pull()
+  gchar *b = (gchar *)(d.dst + P * (size_t)(Z + 1));
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int k = 0; k < 19; ++k)
       __builtin_nontemporal_store(
           v[c][k], (__attribute__((address_space(1))) float *)(
-                       b + (size_t)((own + (uint32_t)(19 * c + k) * nx) * 4u)));
-}
-
-__device__ __forceinline__ void store_node(const Dom &d, int X, int Y, int Z,
-                                           const float (&v)[2][19]) {
-  const uint32_t nx = (uint32_t)d.nx, R = 38u * nx, P = R * (uint32_t)d.ny;
-  uint32_t own = (uint32_t)Y * R + (uint32_t)X;
-  asm volatile("" : "+v"(own));  // per-plane offsets, as in pull()
-  store_plane(d.dst + (size_t)P * (size_t)(Z + 1), own, nx, v);
+                       b + (size_t)((own + (uint32_t)((19 * c + k) * kBN)) * 4u)));
 }
 
 // ---- fused step ------------------------------------------------------------
@@ -315,8 +313,13 @@ __global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(3))) voi
   __shared__ float stage[38][NT];
   __shared__ uint32_t stage_m[NT];
 
+  // lanes follow the storage bricks: 32 consecutive lanes own one 8 x 4
+  // brick, so each population load or store of a wavefront is whole lines
+  static_assert(TX % kBX == 0 && TY % kBY == 0, "tiles are whole bricks");
   const int tid = threadIdx.x;
-  const int tx = tid % TX, ty = tid / TX;
+  const int tb = tid / kBN;
+  const int tx = (tb % (TX / kBX)) * kBX + tid % kBX;
+  const int ty = (tb / (TX / kBX)) * kBY + (tid / kBX) % kBY;
   // list entries are handed out so that each XCD (blocks b = xcd mod 8) gets
   // one contiguous range of the tile list, keeping spatial neighbours in one L2
   const int b = blockIdx.x;
@@ -718,15 +721,15 @@ __global__ void k_init(Dom d, double rho_ref, const double *rho_init, double maj
     const int x = (int)(n % d.nx), y = (int)((n / d.nx) % d.ny), z = (int)(n / ((size_t)d.nx * d.ny));
     // this node's row in its plane and, on a z-periodic subdomain, in the
     // ghost plane that mirrors it
-    float *row = g + P * (size_t)(z + 1) + (size_t)y * 38 * d.nx + x;
+    float *row = g + P * (size_t)(z + 1) + brick_y(y, d.nx) + brick_x(x);
     float *ghost = nullptr;
     if ((d.per & 4) && z == 0) ghost = row + P * (size_t)d.nz;
     if ((d.per & 4) && z == d.nz - 1) ghost = row - P * (size_t)d.nz;
     const uint32_t t = d.mask[n] >> kTypeShift;
     if (t == kSolid) {
       for (int q = 0; q < 38; ++q) {
-        row[(size_t)q * d.nx] = 0.f;
-        if (ghost) ghost[(size_t)q * d.nx] = 0.f;
+        row[(size_t)q * kBN] = 0.f;
+        if (ghost) ghost[(size_t)q * kBN] = 0.f;
       }
       continue;
     }
@@ -739,8 +742,8 @@ __global__ void k_init(Dom d, double rho_ref, const double *rho_init, double maj
       for (int c = 0; c < 2; ++c) {
         const double r = rho0_of(d.mask, rho_init, maj, mnr, z_front, rres, d.N, src, zs, c);
         const float gv = (float)(wd(k) * (r - rho_ref));
-        row[(size_t)(c * 19 + k) * d.nx] = gv;
-        if (ghost) ghost[(size_t)(c * 19 + k) * d.nx] = gv;
+        row[(size_t)(c * 19 + k) * kBN] = gv;
+        if (ghost) ghost[(size_t)(c * 19 + k) * kBN] = gv;
       }
     }
   }

@@ -66,8 +66,12 @@ def test_invalid_arguments_rejected_without_gpu_work():
     P.tau[0] = 1.0
     P.nx = 2
     assert L.lbm_throat_init(ctypes.byref(P), ctypes.byref(h)) == lbm.LBM_EINVAL
-    # the three-plane pull offsets of the row-interleaved storage are 32-bit:
-    # at most 9,418,786 nodes per z-plane (here 4000 x 3000 x 3 nodes)
+    # the three-plane pull offsets of the brick storage are 32-bit: at most
+    # 9,418,786 nodes per z-plane once nx and ny are padded to multiples of 8
+    # and 4 (here 4000 x 3000 x 3 nodes; 3065 x 3073 pads to 3072 x 3076)
+    P.nx, P.ny, P.nz = 3065, 3073, 3
+    assert L.lbm_throat_init(ctypes.byref(P), ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert b"plane" in L.lbm_last_error()
     P.nx, P.ny, P.nz = 4000, 3000, 3
     assert L.lbm_throat_init(ctypes.byref(P), ctypes.byref(h)) == lbm.LBM_EINVAL
     assert b"plane" in L.lbm_last_error()
