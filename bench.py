@@ -12,6 +12,7 @@ oracle timed on this host beside it, and an HBM-bound 512^3 measurement of the
 same kernel.
 """
 import argparse
+import glob
 import hashlib
 import json
 import math
@@ -60,7 +61,7 @@ HYB_SPHERES = 40
 HYB_CONV = dict(tol=1e-6, check_every=100, max_steps=1500, bisect_rel=0.01)
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix cores, vendor figure
 KERNEL_SRC = os.path.join(ROOT, "paper_1906_04722_amd", "csrc", "sc_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_c2_96_traffic.txt")
+TRAFFIC_GLOB = os.path.join(ROOT, "profiles", "k_step_c2_96_*traffic.txt")
 
 
 def log(msg):
@@ -72,22 +73,31 @@ def kernel_sha():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per step launch from the committed counter summary, if it was
-    taken on the current kernel source; else None."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    kv = {}
-    for line in open(TRAFFIC_FILE):
-        if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
-    if kv.get("kernel_sha") != kernel_sha():
-        return None
-    try:
-        return float(kv["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+def read_traffic(schedule):
+    """HBM bytes per step from a committed counter summary of the 96^3 step,
+    taken on the current kernel source with the same launch shape; else None."""
+    want = ",".join(str(int(v)) for v in schedule)
+    for path in sorted(glob.glob(TRAFFIC_GLOB)):
+        kv = {}
+        for line in open(path):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("kernel_sha") == kernel_sha() and kv.get("schedule") == want:
+            try:
+                return float(kv["traffic_bytes_per_launch"])
+            except (KeyError, ValueError):
+                return None
+    return None
+
+
+def step_kernels(schedule):
+    """What one timed step launches for this launch shape."""
+    if schedule[0] == lbm.LBM_SCHED_NODE_LIST:
+        return ("k_dens_list + k_step_list (node-list step: densities of the non-solid nodes, "
+                "then fused pull + cohesion/adhesion + BGK); figures per step")
+    return (f"k_step<{schedule[0]},{schedule[1]}> lz {schedule[2]} (fused pull + moments + "
+            "cohesion/adhesion + BGK)")
 
 
 def c2_workload():
@@ -97,9 +107,13 @@ def c2_workload():
     return p, pcs
 
 
-def one_drain(p, pcs):
+def one_drain(p, pcs, schedule=None):
     g = lbm.Throat(p)
-    sched = g.autotune(20)
+    if schedule:
+        g.set_schedule(*schedule)
+        sched = g.schedule()
+    else:
+        sched = g.autotune(20)
     g.step_timer(1)
     out = g.drain(pcs, **CONV)
     ms, launches = g.step_timer(-1)
@@ -502,6 +516,9 @@ def main():
     ap.add_argument("--no-three", action="store_true")
     ap.add_argument("--sg-train", type=int, default=SG_CFG["train"],
                     help="throats drained to train the surrogate (default 512, at most ~6000)")
+    ap.add_argument("--schedule", default="",
+                    help="launch shape tx,ty,lz of the 96^3 drains (e.g. --schedule=-1,0,0 for "
+                         "the node list) instead of the autotuner's pick")
     ap.add_argument("--paper40", action="store_true",
                     help="also run the replica of the paper's 40-sphere sample (about 2 min)")
     ap.add_argument("--three-radii", default=",".join(f"{v:g}" for v in THREE_CFG["radii"]),
@@ -516,14 +533,15 @@ def main():
         sys.exit(2)
 
     p, pcs = c2_workload()
+    fixed = tuple(int(v) for v in a.schedule.split(",")) if a.schedule else None
     for i in range(a.warmup):
-        one_drain(p, pcs)
+        one_drain(p, pcs, fixed)
         log(f"warmup drain {i + 1}/{a.warmup} done")
 
     t0 = time.perf_counter()
     results = []
     for i in range(a.steps):
-        results.append(one_drain(p, pcs))
+        results.append(one_drain(p, pcs, fixed))
         log(f"timed drain {i + 1}/{a.steps} done")
     dt = time.perf_counter() - t0
 
@@ -561,15 +579,16 @@ def main():
                    "check_every": CONV["check_every"], "max_steps_per_point": CONV["max_steps"]},
         "fluid_MLUPS": round(n_fluid * total_steps / dt / 1e6, 1),
         "lattice_steps_per_drain": total_steps // a.steps,
-        "schedule_autotuned": list(out["schedule"]),
+        "schedule": list(out["schedule"]),
+        "schedule_source": "fixed (--schedule)" if fixed else "autotuned",
         "pce": lbm.nan_safe(out["pce"]),
         "pce_bracket": [out["pce_lo"], lbm.nan_safe(out["pce_hi"])],
         "drainage_curve": {"pc": [round(float(x), 6) for x in pcs],
                            "S_w": [round(float(x), 6) for x in out["S"]]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": read_traffic(),
-                     "kernel": "k_step (fused pull + moments + cohesion/adhesion + BGK)",
+                     "traffic": read_traffic(out["schedule"]),
+                     "kernel": step_kernels(out["schedule"]),
                      "launches": k_launches, "avg_launch_us": round(avg_launch_s * 1e6, 2),
                      "alg_bytes_per_launch": alg_bytes},
     }

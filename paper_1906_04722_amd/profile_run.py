@@ -9,8 +9,10 @@ writer for the counter output.
       launch shape as the benchmark does.
   python3 -m paper_1906_04722_amd.profile_run summarize --stats S.csv
       --fetch F.csv --write W.csv --out profiles/NAME.txt --command "..."
-      writes the per-launch averages of the step kernel, the copy-kernel
-      calibration factors and the calibrated HBM traffic per launch.
+      writes the per-step averages of the step kernels (the fused k_step, or
+      with --kernels k_dens_list,k_step_list the two passes of the node-list
+      step, summed), the copy-kernel calibration factors and the calibrated
+      HBM traffic per step.
 """
 import argparse
 import csv
@@ -72,15 +74,21 @@ def cmd_summarize(a):
     # counters are KiB per dispatch; the copy moves COPY_BYTES each way
     f_scale = COPY_BYTES / (sum(cf) / len(cf) * 1024.0)
     w_scale = COPY_BYTES / (sum(cw) / len(cw) * 1024.0)
-    sf = find(fetch, "k_step")
-    sw = find(write, "k_step")
-    fb = sum(sf) / len(sf) * 1024.0 * f_scale
-    wb = sum(sw) / len(sw) * 1024.0 * w_scale
+    fb = wb = 0.0
+    counted = []
+    for key in a.kernels.split(","):
+        sf = find(fetch, key)
+        sw = find(write, key)
+        fb += sum(sf) / len(sf) * 1024.0 * f_scale
+        wb += sum(sw) / len(sw) * 1024.0 * w_scale
+        counted.append(f"{key} x{len(sf)}")
     sha = hashlib.sha256(open(os.path.join(PKG, "csrc", "sc_kernels.hip"), "rb").read())
     lines = [f"# {a.title}", f"# command: {a.command}",
-             f"kernel_sha: {sha.hexdigest()[:16]}",
-             f"copy_fetch_scale: {f_scale:.4f}", f"copy_write_scale: {w_scale:.4f}",
-             f"step_launches_counted: {len(sf)}",
+             f"kernel_sha: {sha.hexdigest()[:16]}"]
+    if a.schedule:
+        lines.append(f"schedule: {a.schedule}")
+    lines += [f"copy_fetch_scale: {f_scale:.4f}", f"copy_write_scale: {w_scale:.4f}",
+             f"step_launches_counted: {', '.join(counted)}",
              f"fetch_bytes_per_launch: {fb:.0f}", f"write_bytes_per_launch: {wb:.0f}",
              f"traffic_bytes_per_launch: {fb + wb:.0f}"]
     if a.alg_bytes:
@@ -113,6 +121,9 @@ def main():
     s.add_argument("--title", default="fused step")
     s.add_argument("--command", default="")
     s.add_argument("--alg-bytes", type=int, default=0)
+    s.add_argument("--kernels", default="k_step",
+                   help="comma-separated kernel-name keys whose per-dispatch counters make one step")
+    s.add_argument("--schedule", default="", help="launch shape the run used (recorded)")
     a = ap.parse_args()
     cmd_run(a) if a.cmd == "run" else cmd_summarize(a)
 
