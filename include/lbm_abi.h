@@ -235,9 +235,13 @@ int lbm_step_timer(lbm_throat_t h, int enable, double *total_ms, long long *laun
 #define LBM_SCHED_NODE_LIST (-1)
 int lbm_set_schedule(lbm_throat_t h, int tx, int ty, int lz);
 
-/* Autotune the launch shape for this subdomain: time `trial_steps` fused
- * steps for every tile shape and z-segment length (the trials leave the state
- * unchanged), keep the fastest and return it (outputs may be NULL).
+/* Autotune the launch shape for this subdomain: time `trial_steps` steps
+ * for every tile shape and z-segment length and for the node list, in two
+ * rounds of which each candidate keeps its faster one, keep the fastest and
+ * return it (outputs may be NULL).  The trials step the state forward with
+ * alternating buffers, as a drain does, from a copy that is restored at the
+ * end, so the state is unchanged; the copy takes one more population buffer
+ * of device memory while tuning (LBM_ENOMEM if it cannot be had).
  * Synchronous. */
 int lbm_autotune(lbm_throat_t h, int trial_steps, int *tx, int *ty, int *lz);
 int lbm_get_schedule(lbm_throat_t h, int *tx, int *ty, int *lz);

@@ -890,54 +890,68 @@ int lbm_autotune(lbm_throat_t h, int trial_steps, int *tx, int *ty, int *lz) {
     set_err("lbm_autotune: bad handle or trial_steps < 1");
     return LBM_EINVAL;
   }
-  // candidate launch shapes; every trial reads g[cur] and writes g[1-cur]
-  // without flipping, so the state is untouched
+  // Trials advance the state with alternating buffers, as the ramp does (a
+  // trial that re-reads one unchanged buffer times some shapes faster than
+  // they run), from a copy of g[cur] that is put back at the end, also on an
+  // error path.  Every candidate runs an even number of steps, so the newest
+  // state stays in g[cur].  Each is timed in two rounds and keeps its faster
+  // one, so that a slow first pass (clocks, caches) does not decide between
+  // shapes a few per cent apart.
+  struct Keep {
+    lbm_throat *h;
+    float *d = nullptr;
+    size_t bytes = 0;
+    ~Keep() {
+      if (!d) return;
+      (void)hipMemcpyAsync(h->g[h->cur], d, bytes, hipMemcpyDeviceToDevice, h->stream);
+      (void)hipStreamSynchronize(h->stream);
+      (void)hipFree(d);
+    }
+  } keep{h};
+  keep.bytes = sizeof(float) * sc::pop_elems(h->nx, h->ny, h->nz);
+  if (hipMalloc((void **)&keep.d, keep.bytes) != hipSuccess) {
+    keep.d = nullptr;
+    set_err("lbm_autotune: hipMalloc of %zu bytes for the state copy failed", keep.bytes);
+    return LBM_ENOMEM;
+  }
+  HIPCHK(hipMemcpyAsync(keep.d, h->g[h->cur], keep.bytes, hipMemcpyDeviceToDevice, h->stream));
   static const int lzs[7] = {1, 2, 4, 8, 16, 32, 64};
-  const sc::Sched keep = h->sched;
-  sc::Sched best = keep;
-  double best_ms = INFINITY;
+  std::vector<sc::Sched> cand;
   for (const auto &sh : sc::kShapes)
-    for (int l : lzs) {
-      if (l > h->nz) continue;
-      h->sched = sc::Sched{sh[0], sh[1], l};
+    for (int l : lzs)
+      if (l <= h->nz) cand.push_back(sc::Sched{sh[0], sh[1], l});
+  cand.push_back(sc::Sched{sc::kListTx, 0, 0});
+  std::vector<double> t(cand.size(), INFINITY);
+  for (int round = 0; round < 2; ++round)
+    for (size_t c = 0; c < cand.size(); ++c) {
+      const sc::Sched &s = cand[c];
+      h->sched = s;
       TRY(rebuild_tiles(h));
-      for (int w = 0; w < 2; ++w)
-        HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sh[0], sh[1], h->cur, h->stream, h->zper_d, h->n_zper));
+      int par = h->cur;
+      auto one = [&]() {
+        const hipError_t e = sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, s.tx, s.ty, par,
+                                             h->stream, h->zper_d, h->n_zper);
+        par ^= 1;
+        return e;
+      };
+      for (int w = 0; w < 2; ++w) HIPCHK(one());
       HIPCHK(hipEventRecord(h->ev[0], h->stream));
-      for (int i = 0; i < trial_steps; ++i)
-        HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sh[0], sh[1], h->cur, h->stream, h->zper_d, h->n_zper));
+      for (int i = 0; i < trial_steps; ++i) HIPCHK(one());
       HIPCHK(hipEventRecord(h->ev[1], h->stream));
+      if (trial_steps & 1) HIPCHK(one());
       HIPCHK(hipEventSynchronize(h->ev[1]));
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = h->sched;
-      }
+      t[c] = std::min(t[c], (double)ms);
     }
-  {
-    // the node-list path
-    h->sched = sc::Sched{sc::kListTx, 0, 0};
-    TRY(rebuild_tiles(h));
-    for (int w = 0; w < 2; ++w)
-      HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sc::kListTx, 0, h->cur, h->stream, h->zper_d, h->n_zper));
-    HIPCHK(hipEventRecord(h->ev[0], h->stream));
-    for (int i = 0; i < trial_steps; ++i)
-      HIPCHK(sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, sc::kListTx, 0, h->cur, h->stream, h->zper_d, h->n_zper));
-    HIPCHK(hipEventRecord(h->ev[1], h->stream));
-    HIPCHK(hipEventSynchronize(h->ev[1]));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = h->sched;
-    }
-  }
-  h->sched = best;
+  size_t best = 0;
+  for (size_t c = 1; c < cand.size(); ++c)
+    if (t[c] < t[best]) best = c;
+  h->sched = cand[best];
   TRY(rebuild_tiles(h));
-  if (tx) *tx = best.tx;
-  if (ty) *ty = best.ty;
-  if (lz) *lz = best.lz;
+  if (tx) *tx = h->sched.tx;
+  if (ty) *ty = h->sched.ty;
+  if (lz) *lz = h->sched.lz;
   return LBM_OK;
 }
 

@@ -104,49 +104,49 @@ int build_tiles(Batch &B, const sc::Sched &s) {
   return LBM_OK;
 }
 
-// time candidate launch shapes over the whole batch (fixed parity: the
-// trials never change the state) and keep the fastest
+// time candidate launch shapes over the whole batch and keep the fastest.
+// Before the ramp every state is in g[0] and the checkpoint buffers are
+// free: the trials advance the states with alternating buffers, as the ramp
+// does, from copies in save[0] that are put back afterwards.  Each candidate
+// runs an even number of steps and keeps the faster of two timed rounds.
 int autotune(Batch &B, int trial_steps) {
   static const int lzs[5] = {1, 2, 4, 8, 16};
-  sc::Sched best = B.sched;
-  double best_ms = INFINITY;
+  std::vector<sc::Sched> cand;
   for (const auto &sh : sc::kShapes)
-    for (int l : lzs) {
-      const sc::Sched s{sh[0], sh[1], l};
+    for (int l : lzs) cand.push_back(sc::Sched{sh[0], sh[1], l});
+  cand.push_back(sc::Sched{sc::kListTx, 0, 0});
+  for (lbm_throat *x : B.h)
+    BCHK(hipMemcpyAsync(x->save[0], x->g[0], sizeof(float) * sc::pop_elems(x->nx, x->ny, x->nz),
+                        hipMemcpyDeviceToDevice, B.stream));
+  std::vector<double> t(cand.size(), INFINITY);
+  for (int round = 0; round < 2; ++round)
+    for (size_t c = 0; c < cand.size(); ++c) {
+      const sc::Sched &s = cand[c];
       if (int r = build_tiles(B, s)) return r;
-      for (int w = 0; w < 2; ++w)
-        BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream, B.zper_d, B.n_zper));
+      int par = 0;
+      auto one = [&]() {
+        const hipError_t e = sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, par,
+                                             B.stream, B.zper_d, B.n_zper);
+        par ^= 1;
+        return e;
+      };
+      for (int w = 0; w < 2; ++w) BCHK(one());
       BCHK(hipEventRecord(B.ev[0], B.stream));
-      for (int i = 0; i < trial_steps; ++i)
-        BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream, B.zper_d, B.n_zper));
+      for (int i = 0; i < trial_steps; ++i) BCHK(one());
       BCHK(hipEventRecord(B.ev[1], B.stream));
+      if (trial_steps & 1) BCHK(one());
       BCHK(hipEventSynchronize(B.ev[1]));
       float ms = 0.f;
       BCHK(hipEventElapsedTime(&ms, B.ev[0], B.ev[1]));
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = s;
-      }
+      t[c] = std::min(t[c], (double)ms);
     }
-  {
-    // the node-list path
-    const sc::Sched s{sc::kListTx, 0, 0};
-    if (int r = build_tiles(B, s)) return r;
-    for (int w = 0; w < 2; ++w)
-      BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream, B.zper_d, B.n_zper));
-    BCHK(hipEventRecord(B.ev[0], B.stream));
-    for (int i = 0; i < trial_steps; ++i)
-      BCHK(sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, 0, B.stream, B.zper_d, B.n_zper));
-    BCHK(hipEventRecord(B.ev[1], B.stream));
-    BCHK(hipEventSynchronize(B.ev[1]));
-    float ms = 0.f;
-    BCHK(hipEventElapsedTime(&ms, B.ev[0], B.ev[1]));
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = s;
-    }
-  }
-  return build_tiles(B, best);
+  for (lbm_throat *x : B.h)
+    BCHK(hipMemcpyAsync(x->g[0], x->save[0], sizeof(float) * sc::pop_elems(x->nx, x->ny, x->nz),
+                        hipMemcpyDeviceToDevice, B.stream));
+  size_t best = 0;
+  for (size_t c = 1; c < cand.size(); ++c)
+    if (t[c] < t[best]) best = c;
+  return build_tiles(B, cand[best]);
 }
 
 int capture_chunk(Batch &B, const sc::RampCfg &cfg) {

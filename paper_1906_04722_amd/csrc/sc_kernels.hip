@@ -1,10 +1,10 @@
 // sc_kernels.hip -- gfx950 kernels of the two-component Shan-Chen D3Q19
 // update (Montella et al., Sec. 2.1, Eq. 1-5) on one pore-throat subdomain.
 //
-// Storage: shifted FP32 populations g = f - w_k rho_ref; per row of nodes the
-// 38 populations (component-major) are consecutive runs of nx floats, x the
-// unit-stride axis so a wavefront reads and writes 64 consecutive floats per
-// population (layout and ghost planes in sc_internal.h).  The update is a
+// Storage: shifted FP32 populations g = f - w_k rho_ref in bricks of 8 x 4
+// nodes per z-plane, each population of a brick one 128-byte line, so that
+// the 64 lanes of a wavefront read and write two whole lines per population
+// (layout and ghost planes in sc_internal.h).  The update is a
 // pull scheme: buffer `src` holds the post-collision state of step t-1 at
 // each node's own position; pulling g_k from x - e_k gives the pre-collision
 // state f(x, t) of Eq. 1.  One kernel does the whole step: pull + half-way
@@ -529,7 +529,7 @@ static hipError_t step_as(const Throat *th, const TileRef *tiles, int ntiles, in
 
 // Ghost planes of z-periodic subdomains after a step: plane 0 of the new
 // state is copied to plane nz, plane nz - 1 to plane -1 (two contiguous runs
-// of 38 nx ny floats).  Grid: x over the run, y over the listed subdomains.
+// of one padded plane each).  Grid: x over the run, y over the listed subdomains.
 __global__ __launch_bounds__(256) void k_ghost(const Throat *__restrict__ throats,
                                                const int *__restrict__ ids, int parity) {
   const Throat &T = throats[ids[blockIdx.y]];
@@ -719,16 +719,16 @@ __global__ void k_init(Dom d, double rho_ref, const double *rho_init, double maj
   for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < d.N;
        n += (size_t)gridDim.x * blockDim.x) {
     const int x = (int)(n % d.nx), y = (int)((n / d.nx) % d.ny), z = (int)(n / ((size_t)d.nx * d.ny));
-    // this node's row in its plane and, on a z-periodic subdomain, in the
-    // ghost plane that mirrors it
-    float *row = g + P * (size_t)(z + 1) + brick_y(y, d.nx) + brick_x(x);
+    // this node's population 0 in its plane and, on a z-periodic subdomain,
+    // in the ghost plane that mirrors it
+    float *slot = g + P * (size_t)(z + 1) + brick_y(y, d.nx) + brick_x(x);
     float *ghost = nullptr;
-    if ((d.per & 4) && z == 0) ghost = row + P * (size_t)d.nz;
-    if ((d.per & 4) && z == d.nz - 1) ghost = row - P * (size_t)d.nz;
+    if ((d.per & 4) && z == 0) ghost = slot + P * (size_t)d.nz;
+    if ((d.per & 4) && z == d.nz - 1) ghost = slot - P * (size_t)d.nz;
     const uint32_t t = d.mask[n] >> kTypeShift;
     if (t == kSolid) {
       for (int q = 0; q < 38; ++q) {
-        row[(size_t)q * kBN] = 0.f;
+        slot[(size_t)q * kBN] = 0.f;
         if (ghost) ghost[(size_t)q * kBN] = 0.f;
       }
       continue;
@@ -742,7 +742,7 @@ __global__ void k_init(Dom d, double rho_ref, const double *rho_init, double maj
       for (int c = 0; c < 2; ++c) {
         const double r = rho0_of(d.mask, rho_init, maj, mnr, z_front, rres, d.N, src, zs, c);
         const float gv = (float)(wd(k) * (r - rho_ref));
-        row[(size_t)(c * 19 + k) * kBN] = gv;
+        slot[(size_t)(c * 19 + k) * kBN] = gv;
         if (ghost) ghost[(size_t)(c * 19 + k) * kBN] = gv;
       }
     }
