@@ -99,9 +99,11 @@ struct Throat {
   Phys P;
 };
 
-// node-list path: one workgroup of kListBlock threads per kListBlock
-// consecutive entries of a subdomain's node list (TileRef::tile = chunk)
+// node-list path: one workgroup of kListBlock threads per kListNodes
+// consecutive entries of a subdomain's node list (TileRef::tile = chunk), a
+// pair of lanes per node (one per component)
 constexpr int kListBlock = 256;
+constexpr int kListNodes = kListBlock / 2;
 
 // one tile of work: subdomain index and packed tile coordinate
 // tix + ntx * (tiy + nty * tiz)

@@ -412,15 +412,21 @@ __global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(3))) voi
 }
 
 // ---- node-list path ---------------------------------------------------------
-// For subdomains where most nodes are solid (thin throat prisms, packed
-// samples) the tiles above spend their lanes on solid nodes.  Here every lane
-// owns one entry of the non-solid node list: a first pass writes each node's
-// densities (the same FP64 sums rounded to FP32 that the tiles keep in LDS),
-// the second pulls, takes the 18-neighbour density stencil from that array
-// (zero on solid nodes and beyond walls), collides and stores.  Per fluid
-// node the second pass moves the same 304 bytes as the fused step plus the
-// stencil reads, the first pass another 152 + 8.  Results are bit-identical
-// to the tiled step: the same sums, stencil order and collision.
+// For subdomains where most nodes are solid (thin throat prisms, small
+// throats) the tiles above spend their lanes on solid nodes.  Here every
+// non-solid node of the list gets a pair of adjacent lanes, lane c handling
+// component c: a first pass writes each node's densities (the same FP64 sums
+// rounded to FP32 that the tiles keep in LDS), the second pulls, takes the
+// 18-neighbour stencil of the other component's density from that array
+// (zero on solid nodes and beyond walls), collides and stores.  The pair
+// swaps its density and momentum by lane shuffle, so each lane evaluates the
+// collision's shared terms from the same operands in the same order as the
+// one-lane collide(): results are bit-identical to the tiled step.  A pair
+// per node doubles the wavefronts of a small subdomain (a 96^3 throat has
+// about one wavefront of nodes per SIMD) and halves each lane's chain of
+// loads and arithmetic.  Per fluid node the second pass moves the same 304
+// bytes as the fused step plus the stencil reads, the first pass another
+// 152 + 8.
 __device__ __forceinline__ const TileRef &list_ref(const TileRef *__restrict__ tiles, int ntiles) {
   const int b = blockIdx.x;
   const int q = ntiles >> 3, r = ntiles & 7, xcd = b & 7, idx = b >> 3;
@@ -440,33 +446,78 @@ __device__ __forceinline__ Dom list_dom(const Throat &T, int parity) {
   return d;
 }
 
+// one component's half of pull(): the 19 populations of component c
+template <int K>
+__device__ __forceinline__ void pull1_rec(gcchar *b, uint32_t m, uint32_t own, uint32_t P,
+                                          const uint32_t (&py)[3], const uint32_t (&px)[3],
+                                          float (&v)[19]) {
+  constexpr int o = opp(K);
+  const bool cut = (m >> K) & 1u;
+  const uint32_t off =
+      cut ? own + (uint32_t)(o * kBN) : src_index<K>(P, py, px) + (uint32_t)(K * kBN);
+  v[K] = *(const __attribute__((address_space(1))) float *)(b + (size_t)(off * 4u));
+  if constexpr (K + 1 < 19) pull1_rec<K + 1>(b, m, own, P, py, px, v);
+}
+
+__device__ __forceinline__ void pull1(const Dom &d, uint32_t m, int X, int Y, int Z, int c,
+                                      float (&v)[19]) {
+  const uint32_t P = (uint32_t)pop_plane(d.nx, d.ny);
+  gcchar *b = (gcchar *)(d.src + (size_t)P * (size_t)Z) + (size_t)(c * 19 * kBN * 4);
+  uint32_t px[3], py[3];
+  px[0] = brick_x(X == 0 ? d.nx - 1 : X - 1);
+  px[1] = brick_x(X);
+  px[2] = brick_x(X == d.nx - 1 ? 0 : X + 1);
+  py[0] = brick_y(Y == 0 ? d.ny - 1 : Y - 1, d.nx);
+  py[1] = brick_y(Y, d.nx);
+  py[2] = brick_y(Y == d.ny - 1 ? 0 : Y + 1, d.nx);
+  const uint32_t own = P + py[1] + px[1];
+  pull1_rec<0>(b, m, own, P, py, px, v);
+}
+
+__device__ __forceinline__ void store1(const Dom &d, int X, int Y, int Z, int c,
+                                       const float (&v)[19]) {
+  const size_t P = pop_plane(d.nx, d.ny);
+  const uint32_t own = brick_y(Y, d.nx) + brick_x(X) + (uint32_t)(19 * c * kBN);
+  gchar *b = (gchar *)(d.dst + P * (size_t)(Z + 1));
+#pragma unroll
+  for (int k = 0; k < 19; ++k)
+    __builtin_nontemporal_store(
+        v[k], (__attribute__((address_space(1))) float *)(
+                  b + (size_t)((own + (uint32_t)(k * kBN)) * 4u)));
+}
+
+__device__ __forceinline__ void list_coords(const Dom &d, uint32_t n, int &X, int &Y, int &Z) {
+  const uint32_t nx = (uint32_t)d.nx, nxy = nx * (uint32_t)d.ny;
+  Z = (int)(n / nxy);
+  Y = (int)((n - (uint32_t)Z * nxy) / nx);
+  X = (int)(n - (uint32_t)Z * nxy - (uint32_t)Y * nx);
+}
+
 __global__ __launch_bounds__(kListBlock) void k_dens_list(const Throat *__restrict__ throats,
                                                           const TileRef *__restrict__ tiles,
                                                           int ntiles, int parity) {
   const TileRef tr = list_ref(tiles, ntiles);
   const Throat &T = throats[tr.throat];
   if (!T.active) return;
-  const uint32_t i = (uint32_t)tr.tile * kListBlock + threadIdx.x;
+  const uint32_t i = (uint32_t)tr.tile * kListNodes + threadIdx.x / 2;
+  const int c = threadIdx.x & 1;
   if (i >= T.nlist) return;
   const Dom d = list_dom(T, parity);
   const Phys &P = T.P;
   const uint32_t n = T.list[i];
   const uint32_t m = d.mask[n];
   const uint32_t t = m >> kTypeShift;
-  float2 r;
+  float r;
   if (t == kFluid) {
-    const uint32_t nx = (uint32_t)d.nx, nxy = nx * (uint32_t)d.ny;
-    const int Z = (int)(n / nxy), Y = (int)((n - (uint32_t)Z * nxy) / nx);
-    const int X = (int)(n - (uint32_t)Z * nxy - (uint32_t)Y * nx);
-    float v[2][19];
-    pull(d, m, X, Y, Z, v);
-    r = make_float2((float)((acc_t)P.rho_ref + sum19(v[0])), (float)((acc_t)P.rho_ref + sum19(v[1])));
-  } else if (t == kResIn) {
-    r = make_float2(P.rres[0][0], P.rres[0][1]);
+    int X, Y, Z;
+    list_coords(d, n, X, Y, Z);
+    float v[19];
+    pull1(d, m, X, Y, Z, c, v);
+    r = (float)((acc_t)P.rho_ref + sum19(v));
   } else {
-    r = make_float2(P.rres[1][0], P.rres[1][1]);
+    r = P.rres[t == kResIn ? 0 : 1][c];
   }
-  T.rho[n] = r;
+  reinterpret_cast<float *>(T.rho)[2 * (size_t)n + c] = r;
 }
 
 __global__ __launch_bounds__(kListBlock) void k_step_list(const Throat *__restrict__ throats,
@@ -475,38 +526,93 @@ __global__ __launch_bounds__(kListBlock) void k_step_list(const Throat *__restri
   const TileRef tr = list_ref(tiles, ntiles);
   const Throat &T = throats[tr.throat];
   if (!T.active) return;
-  const uint32_t i = (uint32_t)tr.tile * kListBlock + threadIdx.x;
-  if (i >= T.nlist) return;
+  const uint32_t i = (uint32_t)tr.tile * kListNodes + threadIdx.x / 2;
+  const int c = threadIdx.x & 1;
+  if (i >= T.nlist) return;  // both lanes of a pair leave together
   const Dom d = list_dom(T, parity);
   const Phys &P = T.P;
   const uint32_t n = T.list[i];
   const uint32_t m = d.mask[n];
   const uint32_t t = m >> kTypeShift;
-  float v[2][19];
-  const uint32_t nx = (uint32_t)d.nx, nxy = nx * (uint32_t)d.ny;
-  const int Z = (int)(n / nxy), Y = (int)((n - (uint32_t)Z * nxy) / nx);
-  const int X = (int)(n - (uint32_t)Z * nxy - (uint32_t)Y * nx);
+  int X, Y, Z;
+  list_coords(d, n, X, Y, Z);
+  float v[19];
   if (t == kFluid) {
-    pull(d, m, X, Y, Z, v);
-    float Sw[3] = {0, 0, 0}, Sn[3] = {0, 0, 0};
+    pull1(d, m, X, Y, Z, c, v);
+    // stencil of the other component's density (the cohesion of Eq. 4)
+    const float *rho_o = reinterpret_cast<const float *>(T.rho) + (1 - c);
+    float So[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 1; k < 19; ++k) {
       const long long nb = node_of(d, X + ex(k), Y + ey(k), Z + ez(k));
-      const float2 rn = nb < 0 ? make_float2(0.f, 0.f) : T.rho[nb];
-      const float a = wf(k) * rn.x, bb = wf(k) * rn.y;
-      if (ex(k)) { Sw[0] += ex(k) > 0 ? a : -a; Sn[0] += ex(k) > 0 ? bb : -bb; }
-      if (ey(k)) { Sw[1] += ey(k) > 0 ? a : -a; Sn[1] += ey(k) > 0 ? bb : -bb; }
-      if (ez(k)) { Sw[2] += ez(k) > 0 ? a : -a; Sn[2] += ez(k) > 0 ? bb : -bb; }
+      const float a = wf(k) * (nb < 0 ? 0.f : rho_o[2 * nb]);
+      if (ex(k)) So[0] += ex(k) > 0 ? a : -a;
+      if (ey(k)) So[1] += ey(k) > 0 ? a : -a;
+      if (ez(k)) So[2] += ez(k) > 0 ? a : -a;
     }
-    collide(P, m, Sw, Sn, v);
+    // collide(), one component per lane
+    const double drd = sum19(v);
+    const float dr = (float)drd;
+    const float rho = (float)((double)P.rho_ref + drd);
+    float j[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 1; k < 19; ++k) {
+      if (k > opp(k)) continue;
+      const float dk = v[k] - v[opp(k)];
+      if (ex(k)) j[0] += ex(k) > 0 ? dk : -dk;
+      if (ey(k)) j[1] += ey(k) > 0 ? dk : -dk;
+      if (ez(k)) j[2] += ez(k) > 0 ? dk : -dk;
+    }
+    const float rho_p = __shfl_xor(rho, 1);
+    float jp[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) jp[a] = __shfl_xor(j[a], 1);
+    const float rho0 = c == 0 ? rho : rho_p, rho1 = c == 0 ? rho_p : rho;
+    float A[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 1; k < 19; ++k) {
+      const float s = (float)((m >> opp(k)) & 1u) * wf(k);
+      if (ex(k)) A[0] += ex(k) > 0 ? s : -s;
+      if (ey(k)) A[1] += ey(k) > 0 ? s : -s;
+      if (ez(k)) A[2] += ez(k) > 0 ? s : -s;
+    }
+    const float gads = P.Gads[c];
+    float F[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) F[a] = -P.G * rho * So[a] - gads * rho * A[a];
+    const float it0 = P.itau[0], it1 = P.itau[1];
+    const float den = rho0 * it0 + rho1 * it1;
+    float up[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float j0 = c == 0 ? j[a] : jp[a], j1 = c == 0 ? jp[a] : j[a];
+      up[a] = (j0 * it0 + j1 * it1) / den;
+    }
+    const float tc = P.tau[c], itc = P.itau[c];
+    float u[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = up[a] + tc * F[a] / rho;
+    const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double rest = drd;
+#pragma unroll
+    for (int k = 1; k < 19; ++k) {
+      float eu = 0.f;
+      if (ex(k)) eu += ex(k) > 0 ? u[0] : -u[0];
+      if (ey(k)) eu += ey(k) > 0 ? u[1] : -u[1];
+      if (ez(k)) eu += ez(k) > 0 ? u[2] : -u[2];
+      const float geq = wf(k) * (dr + rho * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
+      const float g = v[k];
+      const float gs = g - (g - geq) * itc;
+      v[k] = gs;
+      rest -= (double)gs;
+    }
+    v[0] = (float)rest;
   } else {
     const int b = t == kResIn ? 0 : 1;
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int k = 0; k < 19; ++k) v[c][k] = wf(k) * P.gres[b][c];
+    for (int k = 0; k < 19; ++k) v[k] = wf(k) * P.gres[b][c];
   }
-  store_node(d, X, Y, Z, v);
+  store1(d, X, Y, Z, c, v);
 }
 
 bool schedule_valid(const Sched &s) {
@@ -575,11 +681,11 @@ hipError_t launch_step(const Throat *th, const TileRef *tiles, int ntiles, int t
 
 void list_tiles(const uint8_t *types, int nx, int ny, int nz, int tx, int ty, int lz, int throat,
                 std::vector<TileRef> &out) {
-  if (tx == kListTx) {  // node-list path: chunks of kListBlock non-solid nodes
+  if (tx == kListTx) {  // node-list path: chunks of kListNodes non-solid nodes
     const size_t N = (size_t)nx * ny * nz;
     size_t nl = 0;
     for (size_t n = 0; n < N; ++n) nl += types[n] != kSolid;
-    for (size_t c = 0; c * kListBlock < nl; ++c) out.push_back(TileRef{throat, (int)c});
+    for (size_t c = 0; c * kListNodes < nl; ++c) out.push_back(TileRef{throat, (int)c});
     return;
   }
   const int ntx = (nx + tx - 1) / tx, nty = (ny + ty - 1) / ty, ntz = (nz + lz - 1) / lz;
