@@ -579,12 +579,22 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
               if (h->types[n] != sc::kSolid) list.push_back((uint32_t)n);
             }
     h->nlist = (uint32_t)list.size();
-    ALLOC(h->list_d, sizeof(uint32_t) * std::max<size_t>(list.size(), 1));
+    // each entry carries the node's mask word, which saves the list kernels
+    // one dependent load
+    ALLOC(h->list_d, sizeof(uint2) * std::max<size_t>(list.size(), 1));
     ALLOC(h->rho_d, sizeof(float2) * h->N);
-    if ((!list.empty() && hipMemcpyAsync(h->list_d, list.data(), sizeof(uint32_t) * list.size(),
-                                         hipMemcpyHostToDevice, h->stream) != hipSuccess) ||
-        hipMemsetAsync(h->rho_d, 0, sizeof(float2) * h->N, h->stream) != hipSuccess ||
-        hipStreamSynchronize(h->stream) != hipSuccess) {
+    uint32_t *ids_d = nullptr;
+    ALLOC(ids_d, sizeof(uint32_t) * std::max<size_t>(list.size(), 1));
+    const bool ok =
+        (list.empty() ||
+         (hipMemcpyAsync(ids_d, list.data(), sizeof(uint32_t) * list.size(),
+                         hipMemcpyHostToDevice, h->stream) == hipSuccess &&
+          sc::launch_list_entries(ids_d, h->mask, h->nlist, h->list_d, h->stream) ==
+              hipSuccess)) &&
+        hipMemsetAsync(h->rho_d, 0, sizeof(float2) * h->N, h->stream) == hipSuccess &&
+        hipStreamSynchronize(h->stream) == hipSuccess;
+    (void)hipFree(ids_d);
+    if (!ok) {
       set_err("node list upload failed");
       return fail(LBM_EHIP);
     }

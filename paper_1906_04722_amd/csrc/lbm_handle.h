@@ -20,7 +20,7 @@ struct lbm_throat {
   int cur = 0;                       // g[cur] holds the current state
   float *save[2] = {nullptr, nullptr};  // checkpoints used by the ramp
   uint32_t *mask = nullptr;
-  uint32_t *list_d = nullptr;        // non-solid nodes, storage order (node-list path)
+  uint2 *list_d = nullptr;           // non-solid nodes, storage order, with mask (node-list path)
   uint32_t nlist = 0;
   float2 *rho_d = nullptr;           // densities of the current step (node-list path)
   uint8_t *types_d = nullptr;

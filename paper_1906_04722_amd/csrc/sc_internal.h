@@ -93,7 +93,7 @@ struct Throat {
   int nx, ny, nz, per;
   int ntx, nty, lz;      // tile grid: tiles of TX x TY nodes and lz planes
   int active;            // 0: the launch skips this subdomain
-  const uint32_t *list;  // node-list path: the non-solid nodes, in storage order
+  const uint2 *list;     // node-list path: non-solid nodes in storage order (index, mask word)
   uint32_t nlist;
   float2 *rho;           // node-list path: densities of the current step [N]
   Phys P;
@@ -130,6 +130,9 @@ hipError_t launch_voxelize(const double *spheres, const VoxBins &bins, int prism
                            uint8_t *types, hipStream_t st);
 hipError_t launch_links(const uint8_t *types, int nx, int ny, int nz, int per, uint32_t *mask,
                         hipStream_t st);
+// node-list entries: out[i] = (ids[i], mask[ids[i]]) for i < n
+hipError_t launch_list_entries(const uint32_t *ids, const uint32_t *mask, uint32_t n, uint2 *out,
+                               hipStream_t st);
 hipError_t launch_init(const Dom &d, const Phys &P, const double *rho_init, double rho_major,
                        double rho_minor, int z_front, const double *rres_d, float *g,
                        hipStream_t st);

@@ -493,6 +493,19 @@ __device__ __forceinline__ void list_coords(const Dom &d, uint32_t n, int &X, in
   X = (int)(n - (uint32_t)Z * nxy - (uint32_t)Y * nx);
 }
 
+__global__ void k_list_entries(const uint32_t *ids, const uint32_t *mask, uint32_t n, uint2 *out) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    out[i] = make_uint2(ids[i], mask[ids[i]]);
+}
+
+hipError_t launch_list_entries(const uint32_t *ids, const uint32_t *mask, uint32_t n, uint2 *out,
+                               hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<uint32_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_list_entries, dim3(blocks), dim3(256), 0, st, ids, mask, n, out);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kListBlock) void k_dens_list(const Throat *__restrict__ throats,
                                                           const TileRef *__restrict__ tiles,
                                                           int ntiles, int parity) {
@@ -504,8 +517,8 @@ __global__ __launch_bounds__(kListBlock) void k_dens_list(const Throat *__restri
   if (i >= T.nlist) return;
   const Dom d = list_dom(T, parity);
   const Phys &P = T.P;
-  const uint32_t n = T.list[i];
-  const uint32_t m = d.mask[n];
+  const uint2 e = T.list[i];
+  const uint32_t n = e.x, m = e.y;
   const uint32_t t = m >> kTypeShift;
   float r;
   if (t == kFluid) {
@@ -531,8 +544,8 @@ __global__ __launch_bounds__(kListBlock) void k_step_list(const Throat *__restri
   if (i >= T.nlist) return;  // both lanes of a pair leave together
   const Dom d = list_dom(T, parity);
   const Phys &P = T.P;
-  const uint32_t n = T.list[i];
-  const uint32_t m = d.mask[n];
+  const uint2 e = T.list[i];
+  const uint32_t n = e.x, m = e.y;
   const uint32_t t = m >> kTypeShift;
   int X, Y, Z;
   list_coords(d, n, X, Y, Z);
@@ -540,12 +553,22 @@ __global__ __launch_bounds__(kListBlock) void k_step_list(const Throat *__restri
   if (t == kFluid) {
     pull1(d, m, X, Y, Z, c, v);
     // stencil of the other component's density (the cohesion of Eq. 4)
+    // Neighbour x + e_k is the pull source of direction opp(k): its link bit
+    // says whether it is solid or beyond a wall (density zero); otherwise it
+    // is in the box or across a periodic face.
     const float *rho_o = reinterpret_cast<const float *>(T.rho) + (1 - c);
+    const int xm = X == 0 ? d.nx - 1 : X - 1, xp = X == d.nx - 1 ? 0 : X + 1;
+    const int ym = Y == 0 ? d.ny - 1 : Y - 1, yp = Y == d.ny - 1 ? 0 : Y + 1;
+    const int zm = Z == 0 ? d.nz - 1 : Z - 1, zp = Z == d.nz - 1 ? 0 : Z + 1;
     float So[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 1; k < 19; ++k) {
-      const long long nb = node_of(d, X + ex(k), Y + ey(k), Z + ez(k));
-      const float a = wf(k) * (nb < 0 ? 0.f : rho_o[2 * nb]);
+      const int xn = ex(k) > 0 ? xp : (ex(k) < 0 ? xm : X);
+      const int yn = ey(k) > 0 ? yp : (ey(k) < 0 ? ym : Y);
+      const int zn = ez(k) > 0 ? zp : (ez(k) < 0 ? zm : Z);
+      const uint32_t nb = ((uint32_t)zn * (uint32_t)d.ny + (uint32_t)yn) * (uint32_t)d.nx +
+                          (uint32_t)xn;
+      const float a = wf(k) * (((m >> opp(k)) & 1u) ? 0.f : rho_o[2 * (size_t)nb]);
       if (ex(k)) So[0] += ex(k) > 0 ? a : -a;
       if (ey(k)) So[1] += ey(k) > 0 ? a : -a;
       if (ez(k)) So[2] += ez(k) > 0 ? a : -a;
