@@ -365,6 +365,7 @@ def _hybrid(x, r, L, res, state, name):
             "throat_lbm_s": round(t_lbm, 2), "throats_per_s": round(len(idx) / t_lbm, 2),
             "throats_per_s_one_at_a_time": round(1.0 / t_one, 3),
             "lbm_fluid_MLUPS": round(info["fluid_updates"] / (info["wall_ms"] * 1e3), 1),
+            "schedule": [info["tx"], info["ty"], info["lz"]],
             "network_ms": round(t_net * 1e3, 3), "lbm_over_incircle_median": round(ratio, 4),
             "pressures_per_gamma": [round(float(v), 4) for v in pressures],
             "S_w": [round(float(v), 4) for v in sw],
