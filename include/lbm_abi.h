@@ -236,9 +236,10 @@ int lbm_step_timer(lbm_throat_t h, int enable, double *total_ms, long long *laun
 int lbm_set_schedule(lbm_throat_t h, int tx, int ty, int lz);
 
 /* Autotune the launch shape for this subdomain: time `trial_steps` steps
- * for every tile shape and z-segment length and for the node list, in two
- * rounds of which each candidate keeps its faster one, keep the fastest and
- * return it (outputs may be NULL).  The trials step the state forward with
+ * for every tile shape in increasing z-segment length (up to the first that
+ * is 1.5x slower than the shape's best) and for the node list, time the
+ * candidates within 1.25x of the best once more (each keeps its faster
+ * time), keep the fastest and return it (outputs may be NULL).  The trials step the state forward with
  * alternating buffers, as a drain does, from a copy that is restored at the
  * end, so the state is unchanged; the copy takes one more population buffer
  * of device memory while tuning (LBM_ENOMEM if it cannot be had).

@@ -106,8 +106,8 @@ int sync_desc(lbm_throat *h) {
 // tiles of the current schedule that hold a non-solid node
 int rebuild_tiles(lbm_throat *h) {
   std::vector<sc::TileRef> list;
-  sc::list_tiles(h->types.data(), h->nx, h->ny, h->nz, h->sched.tx, h->sched.ty, h->sched.lz, 0,
-                 list);
+  sc::list_tiles(h->bricks.data(), h->n_nonsolid, h->nx, h->ny, h->nz, h->sched.tx, h->sched.ty,
+                 h->sched.lz, 0, list);
   if (list.size() > h->tiles_cap) {
     if (h->tiles_d) HIPCHK(hipStreamSynchronize(h->stream));
     if (h->tiles_d) (void)hipFree(h->tiles_d);
@@ -511,6 +511,7 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
   long long nf = 0;
   for (size_t n = 0; n < h->N; ++n) nf += h->types[n] == sc::kFluid;
   h->n_fluid = nf;
+  sc::brick_map(h->types.data(), h->nx, h->ny, h->nz, h->bricks, h->n_nonsolid);
 
   if (p->probe[0] >= 0) {
     if (p->probe[0] >= h->nx || p->probe[1] < 0 || p->probe[1] >= h->ny || p->probe[2] < 0 ||
@@ -565,8 +566,7 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
   // path (solid entries stay zero: they are the stencil's solid density)
   {
     std::vector<uint32_t> list;
-    list.reserve((size_t)(h->N - (size_t)std::count(h->types.begin(), h->types.end(),
-                                                     (uint8_t)sc::kSolid)));
+    list.reserve(h->n_nonsolid);
     // in storage order (brick by brick), so that the lanes of a wavefront
     // read and write whole lines of the population buffers
     const size_t nxy = (size_t)h->nx * h->ny;
@@ -904,9 +904,9 @@ int lbm_autotune(lbm_throat_t h, int trial_steps, int *tx, int *ty, int *lz) {
   // trial that re-reads one unchanged buffer times some shapes faster than
   // they run), from a copy of g[cur] that is put back at the end, also on an
   // error path.  Every candidate runs an even number of steps, so the newest
-  // state stays in g[cur].  Each is timed in two rounds and keeps its faster
-  // one, so that a slow first pass (clocks, caches) does not decide between
-  // shapes a few per cent apart.
+  // state stays in g[cur].  The close candidates are timed a second time and
+  // keep their faster time, so that a slow first pass (clocks, caches) does
+  // not decide between shapes a few per cent apart.
   struct Keep {
     lbm_throat *h;
     float *d = nullptr;
@@ -932,28 +932,45 @@ int lbm_autotune(lbm_throat_t h, int trial_steps, int *tx, int *ty, int *lz) {
       if (l <= h->nz) cand.push_back(sc::Sched{sh[0], sh[1], l});
   cand.push_back(sc::Sched{sc::kListTx, 0, 0});
   std::vector<double> t(cand.size(), INFINITY);
-  for (int round = 0; round < 2; ++round)
-    for (size_t c = 0; c < cand.size(); ++c) {
-      const sc::Sched &s = cand[c];
-      h->sched = s;
-      TRY(rebuild_tiles(h));
-      int par = h->cur;
-      auto one = [&]() {
-        const hipError_t e = sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, s.tx, s.ty, par,
-                                             h->stream, h->zper_d, h->n_zper);
-        par ^= 1;
-        return e;
-      };
-      for (int w = 0; w < 2; ++w) HIPCHK(one());
-      HIPCHK(hipEventRecord(h->ev[0], h->stream));
-      for (int i = 0; i < trial_steps; ++i) HIPCHK(one());
-      HIPCHK(hipEventRecord(h->ev[1], h->stream));
-      if (trial_steps & 1) HIPCHK(one());
-      HIPCHK(hipEventSynchronize(h->ev[1]));
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
-      t[c] = std::min(t[c], (double)ms);
+  auto trial = [&](size_t c) -> int {
+    const sc::Sched &s = cand[c];
+    h->sched = s;
+    TRY(rebuild_tiles(h));
+    int par = h->cur;
+    auto one = [&]() {
+      const hipError_t e = sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, s.tx, s.ty, par,
+                                           h->stream, h->zper_d, h->n_zper);
+      par ^= 1;
+      return e;
+    };
+    for (int w = 0; w < 2; ++w) HIPCHK(one());
+    HIPCHK(hipEventRecord(h->ev[0], h->stream));
+    for (int i = 0; i < trial_steps; ++i) HIPCHK(one());
+    HIPCHK(hipEventRecord(h->ev[1], h->stream));
+    if (trial_steps & 1) HIPCHK(one());
+    HIPCHK(hipEventSynchronize(h->ev[1]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+    t[c] = std::min(t[c], (double)ms);
+    return LBM_OK;
+  };
+  // first round: per tile shape in increasing lz, stop once a segment length
+  // is 1.5x slower than the shape's best (longer ones only lengthen the
+  // serial z-march); second round: the candidates within 1.25x of the best
+  for (size_t c = 0; c < cand.size();) {
+    double shape_best = INFINITY;
+    size_t e = c;
+    while (e < cand.size() && cand[e].tx == cand[c].tx && cand[e].ty == cand[c].ty) ++e;
+    for (size_t k = c; k < e; ++k) {
+      TRY(trial(k));
+      if (t[k] > 1.5 * shape_best) break;
+      shape_best = std::min(shape_best, t[k]);
     }
+    c = e;
+  }
+  const double first = *std::min_element(t.begin(), t.end());
+  for (size_t c = 0; c < cand.size(); ++c)
+    if (t[c] <= 1.25 * first) TRY(trial(c));
   size_t best = 0;
   for (size_t c = 1; c < cand.size(); ++c)
     if (t[c] < t[best]) best = c;

@@ -87,7 +87,7 @@ int build_tiles(Batch &B, const sc::Sched &s) {
   std::vector<sc::TileRef> tl;
   for (int t = 0; t < B.n; ++t) {
     const lbm_throat *x = B.h[t];
-    sc::list_tiles(x->types.data(), x->nx, x->ny, x->nz, s.tx, s.ty, s.lz, t, tl);
+    sc::list_tiles(x->bricks.data(), x->n_nonsolid, x->nx, x->ny, x->nz, s.tx, s.ty, s.lz, t, tl);
     const bool tiled = s.tx != sc::kListTx;
     B.th_h[t].ntx = tiled ? (x->nx + s.tx - 1) / s.tx : 0;
     B.th_h[t].nty = tiled ? (x->ny + s.ty - 1) / s.ty : 0;
@@ -108,7 +108,7 @@ int build_tiles(Batch &B, const sc::Sched &s) {
 // Before the ramp every state is in g[0] and the checkpoint buffers are
 // free: the trials advance the states with alternating buffers, as the ramp
 // does, from copies in save[0] that are put back afterwards.  Each candidate
-// runs an even number of steps and keeps the faster of two timed rounds.
+// runs an even number of steps; the close ones are timed twice.
 int autotune(Batch &B, int trial_steps) {
   static const int lzs[5] = {1, 2, 4, 8, 16};
   std::vector<sc::Sched> cand;
@@ -119,27 +119,45 @@ int autotune(Batch &B, int trial_steps) {
     BCHK(hipMemcpyAsync(x->save[0], x->g[0], sizeof(float) * sc::pop_elems(x->nx, x->ny, x->nz),
                         hipMemcpyDeviceToDevice, B.stream));
   std::vector<double> t(cand.size(), INFINITY);
-  for (int round = 0; round < 2; ++round)
-    for (size_t c = 0; c < cand.size(); ++c) {
-      const sc::Sched &s = cand[c];
-      if (int r = build_tiles(B, s)) return r;
-      int par = 0;
-      auto one = [&]() {
-        const hipError_t e = sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, par,
-                                             B.stream, B.zper_d, B.n_zper);
-        par ^= 1;
-        return e;
-      };
-      for (int w = 0; w < 2; ++w) BCHK(one());
-      BCHK(hipEventRecord(B.ev[0], B.stream));
-      for (int i = 0; i < trial_steps; ++i) BCHK(one());
-      BCHK(hipEventRecord(B.ev[1], B.stream));
-      if (trial_steps & 1) BCHK(one());
-      BCHK(hipEventSynchronize(B.ev[1]));
-      float ms = 0.f;
-      BCHK(hipEventElapsedTime(&ms, B.ev[0], B.ev[1]));
-      t[c] = std::min(t[c], (double)ms);
+  auto trial = [&](size_t c) -> int {
+    const sc::Sched &s = cand[c];
+    if (int r = build_tiles(B, s)) return r;
+    int par = 0;
+    auto one = [&]() {
+      const hipError_t e = sc::launch_step(B.th_d, B.tiles_d, B.ntiles, s.tx, s.ty, par,
+                                           B.stream, B.zper_d, B.n_zper);
+      par ^= 1;
+      return e;
+    };
+    for (int w = 0; w < 2; ++w) BCHK(one());
+    BCHK(hipEventRecord(B.ev[0], B.stream));
+    for (int i = 0; i < trial_steps; ++i) BCHK(one());
+    BCHK(hipEventRecord(B.ev[1], B.stream));
+    if (trial_steps & 1) BCHK(one());
+    BCHK(hipEventSynchronize(B.ev[1]));
+    float ms = 0.f;
+    BCHK(hipEventElapsedTime(&ms, B.ev[0], B.ev[1]));
+    t[c] = std::min(t[c], (double)ms);
+    return LBM_OK;
+  };
+  // as the single-subdomain autotuner: per shape in increasing lz until a
+  // segment length is 1.5x slower than the shape's best, then the candidates
+  // within 1.25x of the best once more
+  for (size_t c = 0; c < cand.size();) {
+    double shape_best = INFINITY;
+    size_t e = c;
+    while (e < cand.size() && cand[e].tx == cand[c].tx && cand[e].ty == cand[c].ty) ++e;
+    for (size_t k = c; k < e; ++k) {
+      if (int r = trial(k)) return r;
+      if (t[k] > 1.5 * shape_best) break;
+      shape_best = std::min(shape_best, t[k]);
     }
+    c = e;
+  }
+  const double first = *std::min_element(t.begin(), t.end());
+  for (size_t c = 0; c < cand.size(); ++c)
+    if (t[c] <= 1.25 * first)
+      if (int r = trial(c)) return r;
   for (lbm_throat *x : B.h)
     BCHK(hipMemcpyAsync(x->g[0], x->save[0], sizeof(float) * sc::pop_elems(x->nx, x->ny, x->nz),
                         hipMemcpyDeviceToDevice, B.stream));

@@ -36,6 +36,8 @@ struct lbm_throat {
   double *red_h = nullptr;           // pinned [5]
   hipEvent_t ev[2] = {nullptr, nullptr};
   std::vector<uint8_t> types;
+  std::vector<uint8_t> bricks;       // brick liveness map (sc::brick_map)
+  size_t n_nonsolid = 0;
   long long n_fluid = 0;
   long long probe = -1;
   double tau[2], G, Gads[2], rho_major, rho_minor, rho_in, rho_out;

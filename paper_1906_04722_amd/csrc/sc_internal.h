@@ -142,10 +142,16 @@ hipError_t launch_init(const Dom &d, const Phys &P, const double *rho_init, doub
 // planes are refreshed after the step.
 hipError_t launch_step(const Throat *throats, const TileRef *tiles, int ntiles, int tx, int ty,
                        int parity, hipStream_t st, const int *zper_ids, int n_zper);
+// host: per plane, which 8 x 4 bricks hold a non-solid node ([nz][nyp / 4]
+// [nxp / 8] bytes), and the number of non-solid nodes; computed once per
+// subdomain from its node classes
+void brick_map(const uint8_t *types, int nx, int ny, int nz, std::vector<uint8_t> &live,
+               size_t &nonsolid);
 // host: append the tiles of subdomain `throat` that hold at least one
-// non-solid node (solid-only tiles need no update)
-void list_tiles(const uint8_t *types, int nx, int ny, int nz, int tx, int ty, int lz, int throat,
-                std::vector<TileRef> &out);
+// non-solid node (solid-only tiles need no update), from its brick map; every
+// tile shape is a whole number of bricks
+void list_tiles(const uint8_t *live, size_t nonsolid, int nx, int ny, int nz, int tx, int ty,
+                int lz, int throat, std::vector<TileRef> &out);
 hipError_t launch_export(const Dom &d, const Phys &P, const double *rres_d, double *f,
                          hipStream_t st);
 hipError_t launch_density(const Dom &d, const Phys &P, const double *rres_d, double *rho,

@@ -702,32 +702,48 @@ hipError_t launch_step(const Throat *th, const TileRef *tiles, int ntiles, int t
   return hipGetLastError();
 }
 
-void list_tiles(const uint8_t *types, int nx, int ny, int nz, int tx, int ty, int lz, int throat,
-                std::vector<TileRef> &out) {
+void brick_map(const uint8_t *types, int nx, int ny, int nz, std::vector<uint8_t> &live,
+               size_t &nonsolid) {
+  const int nbx = pad_x(nx) / kBX, nby = pad_y(ny) / kBY;
+  live.assign((size_t)nbx * nby * nz, 0);
+  nonsolid = 0;
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y) {
+      const uint8_t *row = types + (size_t)nx * ((size_t)y + (size_t)ny * z);
+      uint8_t *b = live.data() + (size_t)nbx * ((size_t)(y / kBY) + (size_t)nby * z);
+      for (int x = 0; x < nx; ++x)
+        if (row[x] != kSolid) {
+          b[x / kBX] = 1;
+          ++nonsolid;
+        }
+    }
+}
+
+void list_tiles(const uint8_t *live, size_t nonsolid, int nx, int ny, int nz, int tx, int ty,
+                int lz, int throat, std::vector<TileRef> &out) {
   if (tx == kListTx) {  // node-list path: chunks of kListNodes non-solid nodes
-    const size_t N = (size_t)nx * ny * nz;
-    size_t nl = 0;
-    for (size_t n = 0; n < N; ++n) nl += types[n] != kSolid;
-    for (size_t c = 0; c * kListNodes < nl; ++c) out.push_back(TileRef{throat, (int)c});
+    for (size_t c = 0; c * kListNodes < nonsolid; ++c) out.push_back(TileRef{throat, (int)c});
     return;
   }
+  const int nbx = pad_x(nx) / kBX, nby = pad_y(ny) / kBY;
+  const int bpx = tx / kBX, bpy = ty / kBY;  // bricks per tile side
   const int ntx = (nx + tx - 1) / tx, nty = (ny + ty - 1) / ty, ntz = (nz + lz - 1) / lz;
   // liveness of each (x-tile, y-tile) cell of every plane, then of every z-segment
   std::vector<uint8_t> cell((size_t)ntx * nty * nz, 0);
   for (int z = 0; z < nz; ++z)
-    for (int y = 0; y < ny; ++y) {
-      const uint8_t *row = types + (size_t)nx * ((size_t)y + (size_t)ny * z);
-      uint8_t *c = cell.data() + (size_t)ntx * ((size_t)(y / ty) + (size_t)nty * z);
-      for (int x = 0; x < nx; ++x)
-        if (row[x] != kSolid) c[x / tx] = 1;
+    for (int by = 0; by < nby; ++by) {
+      const uint8_t *b = live + (size_t)nbx * ((size_t)by + (size_t)nby * z);
+      uint8_t *c = cell.data() + (size_t)ntx * ((size_t)(by / bpy) + (size_t)nty * z);
+      for (int bx = 0; bx < nbx; ++bx)
+        if (b[bx]) c[bx / bpx] = 1;
     }
   for (int tz = 0; tz < ntz; ++tz)
     for (int tyi = 0; tyi < nty; ++tyi)
       for (int txi = 0; txi < ntx; ++txi) {
-        bool live = false;
-        for (int z = tz * lz; z < std::min(nz, (tz + 1) * lz) && !live; ++z)
-          live = cell[(size_t)txi + (size_t)ntx * ((size_t)tyi + (size_t)nty * z)] != 0;
-        if (live) out.push_back(TileRef{throat, txi + ntx * (tyi + nty * tz)});
+        bool any = false;
+        for (int z = tz * lz; z < std::min(nz, (tz + 1) * lz) && !any; ++z)
+          any = cell[(size_t)txi + (size_t)ntx * ((size_t)tyi + (size_t)nty * z)] != 0;
+        if (any) out.push_back(TileRef{throat, txi + ntx * (tyi + nty * tz)});
       }
 }
 
