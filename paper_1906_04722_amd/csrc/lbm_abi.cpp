@@ -419,24 +419,7 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
     }
     h->n_zper = 1;
   }
-  {
-    std::vector<sc::Chunk> ch;
-    sc::list_chunks(0, (uint32_t)h->N, ch);
-    h->nchunks = (int)ch.size();
-    ALLOC(h->chunks_d, sizeof(sc::Chunk) * ch.size());
-    ALLOC(h->partials, sizeof(double) * 3 * ch.size());
-    ALLOC(h->chunk_first_d, sizeof(int));
-    ALLOC(h->chunk_count_d, sizeof(int));
-    ALLOC(h->redinfo_d, sizeof(sc::RedInfo));
-    const int first = 0, cnt = h->nchunks;
-    if (hipMemcpy(h->chunks_d, ch.data(), sizeof(sc::Chunk) * ch.size(), hipMemcpyHostToDevice) !=
-            hipSuccess ||
-        hipMemcpy(h->chunk_first_d, &first, sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(h->chunk_count_d, &cnt, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
-      set_err("upload of the reduction chunks failed");
-      return fail(LBM_EHIP);
-    }
-  }
+  ALLOC(h->redinfo_d, sizeof(sc::RedInfo));
   ALLOC(h->red_d, 5 * sizeof(double));
   ALLOC(h->desc_d, sizeof(sc::Throat));
   if (hipHostMalloc((void **)&h->red_h, 5 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -596,6 +579,24 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
     (void)hipFree(ids_d);
     if (!ok) {
       set_err("node list upload failed");
+      return fail(LBM_EHIP);
+    }
+  }
+  // reduction chunks over the node list
+  {
+    std::vector<sc::Chunk> ch;
+    sc::list_red_chunks(0, h->nlist, ch);
+    h->nchunks = (int)ch.size();
+    ALLOC(h->chunks_d, sizeof(sc::Chunk) * std::max<size_t>(ch.size(), 1));
+    ALLOC(h->partials, sizeof(double) * 3 * std::max<size_t>(ch.size(), 1));
+    ALLOC(h->chunk_first_d, sizeof(int));
+    ALLOC(h->chunk_count_d, sizeof(int));
+    const int first = 0, cnt = h->nchunks;
+    if ((!ch.empty() && hipMemcpy(h->chunks_d, ch.data(), sizeof(sc::Chunk) * ch.size(),
+                                  hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(h->chunk_first_d, &first, sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->chunk_count_d, &cnt, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+      set_err("upload of the reduction chunks failed");
       return fail(LBM_EHIP);
     }
   }

@@ -32,8 +32,10 @@ struct Batch {
   int ntiles = 0;
   int *zper_d = nullptr;  // z-periodic subdomains (ghost-plane refresh)
   int n_zper = 0;
-  sc::Chunk *chunks_d = nullptr;
+  sc::Chunk *chunks_d = nullptr;   // reduction chunks (node-list ranges)
   int nchunks = 0;
+  sc::Chunk *cchunks_d = nullptr;  // copy chunks (node ranges) of the checkpoint copies
+  int ncchunks = 0;
   int *first_d = nullptr, *count_d = nullptr;
   sc::RedInfo *info_d = nullptr;
   double *partials = nullptr, *sums = nullptr, *probe = nullptr;
@@ -51,7 +53,8 @@ struct Batch {
   ~Batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    for (void *p : {(void *)th_d, (void *)tiles_d, (void *)zper_d, (void *)chunks_d, (void *)first_d,
+    for (void *p : {(void *)th_d, (void *)tiles_d, (void *)zper_d, (void *)chunks_d, (void *)cchunks_d,
+                    (void *)first_d,
                     (void *)count_d, (void *)info_d, (void *)partials, (void *)sums,
                     (void *)probe, (void *)rd_d, (void *)ck_d, (void *)pc_d, (void *)S_d,
                     (void *)steps_d, (void *)status_d, (void *)nact_d})
@@ -182,7 +185,7 @@ int capture_chunk(Batch &B, const sc::RampCfg &cfg) {
     e = sc::launch_ramp_advance(B.th_d, B.rd_d, B.pc_d, cfg, B.sums, B.probe, B.S_d, B.steps_d,
                                 B.status_d, B.n, B.nact_d, B.stream);
   if (e == hipSuccess)
-    e = sc::launch_copy_requests(B.th_d, B.rd_d, B.ck_d, B.chunks_d, B.nchunks, 0, B.stream);
+    e = sc::launch_copy_requests(B.th_d, B.rd_d, B.ck_d, B.cchunks_d, B.ncchunks, 0, B.stream);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(B.stream, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -236,7 +239,7 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
   BCHK(hipEventCreate(&B.ev[0]));
   BCHK(hipEventCreate(&B.ev[1]));
   // subdomains: geometry, initial state, checkpoints
-  std::vector<sc::Chunk> chunks;
+  std::vector<sc::Chunk> chunks, cchunks;
   std::vector<int> first(n), count(n);
   std::vector<sc::RedInfo> rinfo(n);
   std::vector<sc::RampDev> rd(n);
@@ -260,8 +263,9 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
     B.th_h[t] = x->desc;
     ck[t] = sc::Ckpt{x->save[0], x->save[1]};
     first[t] = (int)chunks.size();
-    sc::list_chunks(t, (uint32_t)x->N, chunks);
+    sc::list_red_chunks(t, x->nlist, chunks);
     count[t] = (int)chunks.size() - first[t];
+    sc::list_chunks(t, (uint32_t)x->N, cchunks);
     rinfo[t] = sc::RedInfo{x->probe, x->phib};
     sc::RampDev R{};
     R.rho_out = x->rho_out;
@@ -272,7 +276,9 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
     rd[t] = R;
   }
   B.nchunks = (int)chunks.size();
-  if (dalloc(&B.th_d, n) || dalloc(&B.chunks_d, chunks.size()) || dalloc(&B.first_d, n) ||
+  B.ncchunks = (int)cchunks.size();
+  if (dalloc(&B.th_d, n) || dalloc(&B.chunks_d, chunks.size()) ||
+      dalloc(&B.cchunks_d, cchunks.size()) || dalloc(&B.first_d, n) ||
       dalloc(&B.count_d, n) || dalloc(&B.info_d, n) || dalloc(&B.partials, 3 * chunks.size()) ||
       dalloc(&B.sums, 3 * (size_t)n) || dalloc(&B.probe, 2 * (size_t)n) || dalloc(&B.rd_d, n) ||
       dalloc(&B.ck_d, n) || dalloc(&B.pc_d, (size_t)n * n_pc) || dalloc(&B.S_d, (size_t)n * n_pc) ||
@@ -283,7 +289,11 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
     set_err("hipHostMalloc failed");
     return LBM_ENOMEM;
   }
-  BCHK(hipMemcpy(B.chunks_d, chunks.data(), sizeof(sc::Chunk) * chunks.size(),
+  if (!cchunks.empty())
+    BCHK(hipMemcpy(B.cchunks_d, cchunks.data(), sizeof(sc::Chunk) * cchunks.size(),
+                   hipMemcpyHostToDevice));
+  if (!chunks.empty())
+    BCHK(hipMemcpy(B.chunks_d, chunks.data(), sizeof(sc::Chunk) * chunks.size(),
                  hipMemcpyHostToDevice));
   BCHK(hipMemcpy(B.first_d, first.data(), sizeof(int) * n, hipMemcpyHostToDevice));
   BCHK(hipMemcpy(B.count_d, count.data(), sizeof(int) * n, hipMemcpyHostToDevice));
@@ -317,7 +327,7 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
                                 B.stream));
   BCHK(sc::launch_reduce_throats(B.first_d, B.count_d, n, B.partials, B.sums, B.stream));
   BCHK(sc::launch_ramp_begin(B.th_d, B.rd_d, B.pc_d, cfg, B.sums, n, B.stream));
-  BCHK(sc::launch_copy_requests(B.th_d, B.rd_d, B.ck_d, B.chunks_d, B.nchunks, 0, B.stream));
+  BCHK(sc::launch_copy_requests(B.th_d, B.rd_d, B.ck_d, B.cchunks_d, B.ncchunks, 0, B.stream));
   if (int r = capture_chunk(B, cfg)) return r;
   // replay until every subdomain has finished its ramp; a bound on the
   // replays guards against a run that would never end

@@ -156,9 +156,12 @@ hipError_t launch_export(const Dom &d, const Phys &P, const double *rres_d, doub
                          hipStream_t st);
 hipError_t launch_density(const Dom &d, const Phys &P, const double *rres_d, double *rho,
                           hipStream_t st);
-// chunked FP64 reduction over subdomains: each chunk is a node range of one
-// subdomain; per chunk the partial sums of rho_w, rho_nw and the saturation
-// term over fluid nodes, then per subdomain the sum of its chunks in order
+// chunked FP64 reduction over subdomains: each reduction chunk is a range of
+// kRedEntries entries of one subdomain's node list; per chunk the partial
+// sums of rho_w, rho_nw and the saturation term over its fluid nodes, then
+// per subdomain the sum of its chunks in order.  Copy chunks (the batch's
+// checkpoint copies) split each subdomain's buffer by node ranges of
+// kChunkNodes instead, so that a copy gets blocks in proportion to its size.
 struct Chunk {
   int throat;
   uint32_t start, count;
@@ -168,7 +171,9 @@ struct RedInfo {
   double phib;      // bulk order parameter of the saturation map
 };
 constexpr uint32_t kChunkNodes = 4096;
+constexpr uint32_t kRedEntries = 1024;
 void list_chunks(int throat, uint32_t N, std::vector<Chunk> &out);
+void list_red_chunks(int throat, uint32_t nlist, std::vector<Chunk> &out);
 // partials[c][3]; probe_out[t][2] = densities at subdomain t's probe node
 hipError_t launch_reduce_chunks(const Throat *th, const Chunk *chunks, int nchunks,
                                 const RedInfo *info, int parity, double *partials,

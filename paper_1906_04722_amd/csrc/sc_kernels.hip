@@ -975,6 +975,11 @@ void list_chunks(int throat, uint32_t N, std::vector<Chunk> &out) {
     out.push_back(Chunk{throat, s, std::min(kChunkNodes, N - s)});
 }
 
+void list_red_chunks(int throat, uint32_t nlist, std::vector<Chunk> &out) {
+  for (uint32_t s = 0; s < nlist; s += kRedEntries)
+    out.push_back(Chunk{throat, s, std::min(kRedEntries, nlist - s)});
+}
+
 __device__ __forceinline__ void block_sum(double (&v)[kRedVals], double (*sh)[kRedThreads]) {
   const int t = threadIdx.x;
 #pragma unroll
@@ -1011,8 +1016,8 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_chunks(const Throat *__r
   const RedInfo ri = info[ch.throat];
   double acc[kRedVals] = {0.0, 0.0, 0.0};
   for (uint32_t i = threadIdx.x; i < ch.count; i += kRedThreads) {
-    const uint32_t n = ch.start + i;
-    const uint32_t m = d.mask[n];
+    const uint2 e = T.list[ch.start + i];
+    const uint32_t n = e.x, m = e.y;
     if ((m >> kTypeShift) != kFluid) continue;
     const int x = (int)(n % (uint32_t)d.nx), y = (int)((n / (uint32_t)d.nx) % (uint32_t)d.ny);
     const int z = (int)(n / ((uint32_t)d.nx * (uint32_t)d.ny));
