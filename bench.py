@@ -13,7 +13,6 @@ same kernel.
 """
 import argparse
 import glob
-import hashlib
 import json
 import math
 import os
@@ -70,7 +69,8 @@ def log(msg):
 
 
 def kernel_sha():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    from paper_1906_04722_amd.profile_run import kernel_sha as sha
+    return sha(KERNEL_SRC)
 
 
 def read_traffic(schedule):

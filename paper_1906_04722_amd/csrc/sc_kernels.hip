@@ -414,11 +414,12 @@ __global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(3))) voi
 // ---- node-list path ---------------------------------------------------------
 // For subdomains where most nodes are solid (thin throat prisms, small
 // throats) the tiles above spend their lanes on solid nodes.  Here every
-// non-solid node of the list gets a pair of adjacent lanes, lane c handling
-// component c: a first pass writes each node's densities (the same FP64 sums
-// rounded to FP32 that the tiles keep in LDS), the second pulls, takes the
-// 18-neighbour stencil of the other component's density from that array
-// (zero on solid nodes and beyond walls), collides and stores.  The pair
+// non-solid node of the list (each entry: node index and mask word) gets a
+// pair of adjacent lanes, lane c handling component c: a first pass writes
+// each node's densities (the same FP64 sums rounded to FP32 that the tiles
+// keep in LDS), the second pulls, takes the 18-neighbour stencil of the
+// other component's density from that array (zero where the node's link
+// bits mark a solid neighbour or a wall), collides and stores.  The pair
 // swaps its density and momentum by lane shuffle, so each lane evaluates the
 // collision's shared terms from the same operands in the same order as the
 // one-lane collide(): results are bit-identical to the tiled step.  A pair
@@ -426,7 +427,7 @@ __global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(3))) voi
 // about one wavefront of nodes per SIMD) and halves each lane's chain of
 // loads and arithmetic.  Per fluid node the second pass moves the same 304
 // bytes as the fused step plus the stencil reads, the first pass another
-// 152 + 8.
+// 152 + 8, and each pass reads the 8-byte list entry.
 __device__ __forceinline__ const TileRef &list_ref(const TileRef *__restrict__ tiles, int ntiles) {
   const int b = blockIdx.x;
   const int q = ntiles >> 3, r = ntiles & 7, xcd = b & 7, idx = b >> 3;

@@ -18,11 +18,23 @@ import argparse
 import csv
 import hashlib
 import os
+import re
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 COPY_BYTES = 1 << 30
+KERNEL_SRC = os.path.join(PKG, "csrc", "sc_kernels.hip")
+
+_TOKENS = re.compile(r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\])*"|[^\s"/]+|/', re.S)
+
+
+def kernel_sha(path=KERNEL_SRC):
+    """Hash of the kernel source's code: comments dropped, tokens separated by
+    single spaces, so that a counter summary stays valid across edits of the
+    comments and layout only."""
+    code = [t for t in _TOKENS.findall(open(path).read()) if not t.startswith(("//", "/*"))]
+    return hashlib.sha256(" ".join(code).encode()).hexdigest()[:16]
 
 
 def cmd_run(a):
@@ -82,9 +94,8 @@ def cmd_summarize(a):
         fb += sum(sf) / len(sf) * 1024.0 * f_scale
         wb += sum(sw) / len(sw) * 1024.0 * w_scale
         counted.append(f"{key} x{len(sf)}")
-    sha = hashlib.sha256(open(os.path.join(PKG, "csrc", "sc_kernels.hip"), "rb").read())
     lines = [f"# {a.title}", f"# command: {a.command}",
-             f"kernel_sha: {sha.hexdigest()[:16]}"]
+             f"kernel_sha: {kernel_sha()}"]
     if a.schedule:
         lines.append(f"schedule: {a.schedule}")
     lines += [f"copy_fetch_scale: {f_scale:.4f}", f"copy_write_scale: {w_scale:.4f}",
