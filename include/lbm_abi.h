@@ -128,8 +128,11 @@ typedef struct {
 typedef struct lbm_throat *lbm_throat_t;
 
 /* Create a subdomain: voxelize the geometry on the device, allocate two FP32
- * population buffers (2 x 152 bytes per node) and set the equilibrium state
- * f = f_eq(rho_init, u = 0) (Eq. 1-3).  *out receives the handle.
+ * population buffers (2 x 152 bytes per node, nx and ny padded to multiples
+ * of 8 and 4) and set the equilibrium state f = f_eq(rho_init, u = 0)
+ * (Eq. 1-3).  Also per node: a 4-byte mask word, a 1-byte class and an
+ * 8-byte density slot of the node-list path; per non-solid node an 8-byte
+ * list entry.  *out receives the handle.
  * Errors: LBM_EINVAL (sizes < 3, tau <= 0.5, non-positive or non-finite
  * densities, bad prism ids, probe outside the fluid), LBM_ENOMEM, LBM_EHIP. */
 int lbm_throat_init(const lbm_params *p, lbm_throat_t *out);
@@ -208,7 +211,8 @@ typedef struct {
  * device between chunks of c->check_every steps (even), captured once as a
  * HIP graph and replayed until every subdomain is done.  The launch shape is
  * autotuned over the whole batch.  Device memory: 4 x 152 bytes per node
- * (two buffers and two ramp checkpoints) plus masks.  Synchronous.  Returns
+ * (two buffers and two ramp checkpoints) plus what lbm_throat_init holds per
+ * subdomain.  Synchronous.  Returns
  * LBM_WNOTCONV if a point hit its cap, LBM_WPARTIAL if a subdomain became
  * non-finite (its points carry LBM_PT_NONFINITE; the others are complete).
  * info may be NULL. */
