@@ -94,11 +94,15 @@ def test_populations_ragged_and_periodic(maker):
     assert err <= 1e-5
 
 
-def test_schedules_agree_bitwise():
-    """The tiling of the fused step does not change any result bit: every
-    node's update reads the same values in the same order whatever the tile."""
+@pytest.mark.parametrize("maker", [_ragged_problem, _periodic_problem])
+def test_schedules_agree_bitwise(maker):
+    """The launch shape does not change any result bit: every node's update
+    reads the same values in the same order whatever the tile, and the node
+    list (lane pairs) evaluates the same sums in the same order.  The ragged
+    box has walls in x, a periodic y and baths in z; the other box is
+    periodic on all three axes (ghost planes, wrapped pulls and stencils)."""
     lbm = _lbm()
-    p = _ragged_problem()
+    p = maker()
     ref = None
     for tx, ty, lz in [(64, 4, 16), (32, 4, 3), (32, 8, 29), (64, 4, 1), (32, 8, 7), (64, 4, 2), (16, 4, 5),
                        (16, 8, 1), (8, 8, 9), (lbm.LBM_SCHED_NODE_LIST, 0, 0)]:
