@@ -219,26 +219,34 @@ def surrogate_leg():
     err_acc = np.abs(res["pce"][acc] - pref[acc]) / pref[acc]
     # the network alone (no fallback) and the accept/fallback trade-off at
     # other thresholds (final answer: LBM where flagged, network elsewhere);
-    # the no-network estimate is the training mean of p_c^e r_open over r_open
-    Fte, r_open = surrogate.describe(te, with_opening=True)
-    base = np.abs(T[:, 0].mean() / r_open[ok] - pref[ok]) / pref[ok]
+    # the no-network estimates are the training means of p_c^e r over r, for
+    # r the MS-P radius (the network's target scale) and the opening radius
+    from paper_1906_04722_amd import estimators as est
+    Fte, r_msp = surrogate.describe(te, with_scale=True)
+    ok = ok & np.isfinite(r_msp)
+    base = np.abs(T[:, 0].mean() / r_msp[ok] - pref[ok]) / pref[ok]
+    circ = lambda probs: [[(s[0], s[1], s[3]) for s in np.asarray(p.spheres)[list(p.prism_ids)]]
+                          for p in probs]
+    ro_tr = np.array([est.opening_radius(c) for c in circ(tr)])
+    ro_te = np.array([est.opening_radius(c) for c in circ(te)])
+    pce_tr = np.array([d["pce"] for d in drains])
+    fin = np.isfinite(pce_tr) & np.isfinite(ro_tr)
+    base_in = np.abs(np.mean(pce_tr[fin] * ro_tr[fin]) / ro_te[ok] - pref[ok]) / pref[ok]
     mean, std = m.predict(Fte)
-    raw = mean[:, 0] / r_open
+    raw = mean[:, 0] / r_msp
     err_raw = np.abs(raw[ok] - pref[ok]) / pref[ok]
     trade = []
     for thr in (0.02, 0.05, 0.1, 0.2):
         take = (std[:, 0] <= thr * np.abs(mean[:, 0]))[ok]
-        fin = np.where(take, err_raw, 0.0)
+        fin_e = np.where(take, err_raw, 0.0)
         trade.append({"threshold": thr, "answered_by_network": round(float(take.mean()), 4),
-                      "final_err_median": round(float(np.median(fin)), 4),
-                      "final_within_1pct": round(float((fin <= 0.01).mean()), 4),
+                      "final_err_median": round(float(np.median(fin_e)), 4),
+                      "final_within_1pct": round(float((fin_e <= 0.01).mean()), 4),
                       "network_err_median_where_answered":
                           round(float(np.median(err_raw[take])), 4) if take.any() else None})
     # the calibrated no-LBM estimate of the paper's cheap methods: MS-P on the
     # throat's cross-section, scaled by its median LBM/MS-P ratio on the
     # training throats
-    from paper_1906_04722_amd import estimators as est
-
     def msp_pc(probs):
         out = []
         for p in probs:
@@ -249,7 +257,6 @@ def surrogate_leg():
     t0 = time.perf_counter()
     msp_te = msp_pc(te)
     t_msp = time.perf_counter() - t0
-    pce_tr = np.array([d["pce"] for d in drains])
     msp_tr = msp_pc(tr)
     fin = np.isfinite(pce_tr) & np.isfinite(msp_tr)
     k_msp = float(np.median(pce_tr[fin] / msp_tr[fin]))
@@ -274,7 +281,8 @@ def surrogate_leg():
             "pce_err_median": round(float(np.median(err)), 4),
             "pce_within_1pct": round(float((err <= 0.01).mean()), 4),
             "accepted_err_median": round(float(np.median(err_acc)), 4) if acc.any() else None,
-            "baseline_mean_err_median": round(float(np.median(base)), 4),
+            "baseline_msp_mean_err_median": round(float(np.median(base)), 4),
+            "baseline_incircle_mean_err_median": round(float(np.median(base_in)), 4),
             "msp_lbm_ratio_train_median": round(k_msp, 4),
             "msp_calibrated_err_median": round(float(np.median(err_msp)), 4),
             "msp_calibrated_within_5pct": round(float((err_msp <= 0.05).mean()), 4),

@@ -21,14 +21,17 @@
  * the box (sample i of an axis of n nodes at (i + 0.5) n / 32 - 0.5; solid
  * means inside a sphere or outside the prism, as the voxelizer decides).
  *
- * Targets (17 values per throat): p_c^e * r_open (lattice pressure times
+ * Targets (17 values per throat): p_c^e * r_msp (lattice pressure times
  * lattice length, in units of the interfacial tension of the model), then
  * the wetting saturation at the 16 points of the drainage ramp the training
- * data were produced with.  r_open is the radius of the throat opening: the
- * circle in the prism's cross-section tangent to the three throat-sphere
- * circles (lbm_surrogate_describe returns it).  The incircle estimate of a
- * perfectly wetting throat makes p_c^e * r_open about 2 gamma, so the
- * network learns how each throat departs from that estimate.
+ * data were produced with.  r_msp is the Mayer-Stowe-Princen corner-meniscus
+ * radius at entry of the throat's cross-section (Sec. 1 of the paper names
+ * the method): the plane of the three throat-sphere centres, the triangle of
+ * centres (the prism's walls) minus the three circles, and the root r of the
+ * force balance A_n = r (L_nw + L_ns) of a perfectly wetting solid, whose
+ * entry pressure is gamma / r (lbm_surrogate_describe returns it).  So
+ * p_c^e * r_msp is about gamma, and the network learns how each throat
+ * departs from that estimate.
  *
  * Conventions as in lbm_abi.h: status codes LBM_*, host arrays owned by the
  * caller, lbm_last_error() for the message of the last failure.
@@ -89,9 +92,10 @@ int lbm_surrogate_set_stats(lbm_surrogate_t m, const double *xmu, const double *
 int lbm_surrogate_get_stats(lbm_surrogate_t m, double *xmu, double *xsd, double *tmu, double *tsd);
 
 /* Descriptors of n throats (each exactly 4 spheres with a prism closure) on
- * the GPU; feat: host [n][80]; r_open: host [n] opening radii in lattice
- * units (0 where the circles leave no gap), or NULL. */
-int lbm_surrogate_describe(int n, const lbm_params *p, double *feat, double *r_open);
+ * the GPU; feat: host [n][80]; r_msp: host [n] MS-P corner-meniscus radii at
+ * entry in lattice units (NaN where the balance has no root before the
+ * menisci meet), or NULL. */
+int lbm_surrogate_describe(int n, const lbm_params *p, double *feat, double *r_msp);
 
 /* Raw ensemble forward on standardised inputs xs (host [n][80]): y host
  * [members][n][17] FP32, standardised outputs. */
@@ -120,7 +124,8 @@ int lbm_surrogate_predict(lbm_surrogate_t m, int n, const double *feat, double *
 /* Entry pressure of n throats: describe, predict, and where the ensemble std
  * of output 0 exceeds threshold * |mean| (and run_fallback is 1) drain the
  * throat with lbm_drain_batch over pc (host [n][n_pc], n_pc = 16) and c, and
- * take its result.  The network's p_c^e is output 0 divided by r_open.
+ * take its result.  The network's p_c^e is output 0 divided by r_msp; a
+ * throat without an MS-P radius is always drained by the LBM.
  * pce [n], curve [n][16], pce_std [n] (ensemble std of p_c^e; 0 where the
  * LBM answered), used_fallback [n] (0/1) are host outputs; info may be NULL.
  * Returns the fallback batch's warning code if any. */

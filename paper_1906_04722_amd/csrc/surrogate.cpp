@@ -309,48 +309,126 @@ int forward_chunks(lbm_surrogate_t s, const float *xs_d, int n, F sink) {
   return LBM_OK;
 }
 
-// Radius of the throat opening: the circle in the prism's cross-section
-// (the xy-plane) tangent to the three throat-sphere circles (centres and
-// radii as given) from the outside, i.e. the Apollonius circle in the gap.
-// Subtracting the tangency conditions pairwise makes the centre linear in the
-// radius, c = u + v r; the first condition then gives a quadratic in r whose
-// smallest positive root is the gap circle.  Returns 0 if the circles leave
-// no gap (or the centres are collinear).
-double opening_radius(const double *G) {
-  const double x0 = G[0], y0 = G[1], r0 = G[3];
-  double A[2][2], b[2], d[2];
-  for (int i = 1; i <= 2; ++i) {
-    const double xi = G[4 * i], yi = G[4 * i + 1], ri = G[4 * i + 3];
-    A[i - 1][0] = 2.0 * (x0 - xi);
-    A[i - 1][1] = 2.0 * (y0 - yi);
-    b[i - 1] = ri * ri - r0 * r0 - (xi * xi + yi * yi) + (x0 * x0 + y0 * y0);
-    d[i - 1] = 2.0 * (ri - r0);
+// Mayer-Stowe-Princen entry radius of the throat's cross-section (Sec. 1 of
+// the paper names the method): the triangle of the three throat-sphere
+// centres (the prism's walls run along its edges) minus the three circles.
+// With corner menisci of radius r the wetting phase holds, per edge: where
+// the circles overlap or touch, the corner closed by the arc tangent to both;
+// where they leave a gap, the two right-angled circle-wall corners, each
+// closed by the arc tangent to its circle and the wall, or the whole gap once
+// those two arcs would meet (closed by the arc tangent to both circles).  The
+// non-wetting phase takes the rest, area A_n, bounded by the menisci (L_nw),
+// the remaining circle arcs and the dry wall segments (L_ns); entry is the
+// root of the force balance A_n = r (L_nw + L_ns) for a perfectly wetting
+// solid, and p_c = gamma / r.
+double half_lens(double a, double b, double d) {
+  if (d >= a + b) return 0.0;
+  const double ca = std::max(-1.0, std::min(1.0, (d * d + a * a - b * b) / (2.0 * d * a)));
+  const double cb = std::max(-1.0, std::min(1.0, (d * d + b * b - a * a) / (2.0 * d * b)));
+  const double k = std::max(0.0, (-d + a + b) * (d + a - b) * (d - a + b) * (d + a + b));
+  return 0.5 * (a * a * std::acos(ca) + b * b * std::acos(cb) - 0.5 * std::sqrt(k));
+}
+
+double vertex_angle(const double *p, const double *q, const double *s) {
+  const double u[2] = {q[0] - p[0], q[1] - p[1]}, v[2] = {s[0] - p[0], s[1] - p[1]};
+  const double c = (u[0] * v[0] + u[1] * v[1]) / (std::hypot(u[0], u[1]) * std::hypot(v[0], v[1]));
+  return std::acos(std::max(-1.0, std::min(1.0, c)));
+}
+
+struct Section {
+  double C[3][2], R[3];
+};
+
+// (A_n, L_nw + L_ns) for corner menisci of radius r; false when the menisci
+// would overlap or leave no non-wetting area
+bool msp_parts(const Section &S, double r, double &An, double &L) {
+  const double pi = 3.14159265358979323846;
+  double area = 0.5 * std::fabs((S.C[1][0] - S.C[0][0]) * (S.C[2][1] - S.C[0][1]) -
+                                (S.C[2][0] - S.C[0][0]) * (S.C[1][1] - S.C[0][1]));
+  double theta[3], used[3] = {0.0, 0.0, 0.0}, wet = 0.0;
+  L = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    const int j = (i + 1) % 3, k = (i + 2) % 3;
+    theta[i] = vertex_angle(S.C[i], S.C[j], S.C[k]);
+    const double d = std::hypot(S.C[j][0] - S.C[i][0], S.C[j][1] - S.C[i][1]);
+    area += -0.5 * S.R[i] * S.R[i] * theta[i] + half_lens(S.R[i], S.R[j], d);
   }
-  const double det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
-  if (!(std::fabs(det) > 0)) return 0.0;
-  const double u[2] = {(A[1][1] * b[0] - A[0][1] * b[1]) / det,
-                       (A[0][0] * b[1] - A[1][0] * b[0]) / det};
-  const double v[2] = {(A[1][1] * d[0] - A[0][1] * d[1]) / det,
-                       (A[0][0] * d[1] - A[1][0] * d[0]) / det};
-  const double w[2] = {u[0] - x0, u[1] - y0};
-  const double qa = v[0] * v[0] + v[1] * v[1] - 1.0;
-  const double qb = 2.0 * (w[0] * v[0] + w[1] * v[1] - r0);
-  const double qc = w[0] * w[0] + w[1] * w[1] - r0 * r0;
-  double best = 0.0;
-  auto take = [&](double r) {
-    if (r > 0 && (best == 0.0 || r < best)) best = r;
-  };
-  if (std::fabs(qa) < 1e-14) {
-    if (qb != 0) take(-qc / qb);
-  } else {
-    const double disc = qb * qb - 4.0 * qa * qc;
-    if (disc >= 0) {
-      const double sq = std::sqrt(disc);
-      take((-qb - sq) / (2.0 * qa));
-      take((-qb + sq) / (2.0 * qa));
+  for (int i = 0; i < 3; ++i) {
+    const int j = (i + 1) % 3;
+    const double d = std::hypot(S.C[j][0] - S.C[i][0], S.C[j][1] - S.C[i][1]);
+    if (S.R[i] + S.R[j] < d) {
+      const double fi = std::sqrt((S.R[i] + r) * (S.R[i] + r) - r * r);
+      const double fj = std::sqrt((S.R[j] + r) * (S.R[j] + r) - r * r);
+      if (fi + fj <= d) {  // two circle-wall corners and a dry wall segment
+        const double f2[2] = {fi, fj};
+        const int q2[2] = {i, j};
+        for (int e = 0; e < 2; ++e) {
+          const double g = std::atan2(r, f2[e]), Rq = S.R[q2[e]];
+          wet += 0.5 * f2[e] * r - 0.5 * Rq * Rq * g - 0.5 * r * r * (0.5 * pi - g);
+          L += r * (0.5 * pi - g);
+          used[q2[e]] += g;
+        }
+        L += d - fi - fj;
+        continue;
+      }
     }
+    // the corner (or the whole gap) closed by the arc tangent to both circles
+    const double a = S.R[i] + r, b = S.R[j] + r;
+    const double ai = std::acos(std::max(-1.0, std::min(1.0, (d * d + a * a - b * b) / (2.0 * d * a))));
+    const double aj = std::acos(std::max(-1.0, std::min(1.0, (d * d + b * b - a * a) / (2.0 * d * b))));
+    const double beta = pi - ai - aj;
+    wet += 0.5 * d * a * std::sin(ai) - 0.5 * S.R[i] * S.R[i] * ai - 0.5 * S.R[j] * S.R[j] * aj -
+           0.5 * r * r * beta + half_lens(S.R[i], S.R[j], d);
+    L += r * beta;
+    used[i] += ai;
+    used[j] += aj;
   }
-  return best;
+  bool valid = true;
+  for (int i = 0; i < 3; ++i) {
+    const double rest = theta[i] - used[i];
+    valid = valid && rest >= 0.0;
+    L += S.R[i] * std::max(rest, 0.0);
+  }
+  An = area - wet;
+  return valid && An > 0.0;
+}
+
+// MS-P corner-meniscus radius at entry of the throat whose three spheres are
+// G[0..11] (x, y, z, R each; the cross-section is the xy-plane), or NaN where
+// no root lies in the range of valid radii: scan r upward by factors of 1.15
+// from 1e-6 of the largest radius until the balance changes sign, then bisect
+// the bracket to 1e-13 of that radius.
+double msp_radius(const double *G) {
+  Section S;
+  double scale = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    S.C[i][0] = G[4 * i];
+    S.C[i][1] = G[4 * i + 1];
+    S.R[i] = G[4 * i + 3];
+    scale = std::max(scale, S.R[i]);
+  }
+  auto f = [&](double r) {
+    double An, L;
+    msp_parts(S, r, An, L);
+    return An - r * L;
+  };
+  double r = 1e-6 * scale;
+  if (!(f(r) > 0.0)) return NAN;
+  for (;;) {
+    const double nxt = r * 1.15;
+    double An, L;
+    if (!msp_parts(S, nxt, An, L)) return NAN;
+    if (An - nxt * L < 0.0) {
+      double lo = r, hi = nxt;
+      while (hi - lo > 1e-13 * scale) {
+        const double mid = 0.5 * (lo + hi);
+        (f(mid) > 0.0 ? lo : hi) = mid;
+      }
+      return 0.5 * (lo + hi);
+    }
+    r = nxt;
+    if (r > 10.0 * scale) return NAN;
+  }
 }
 
 int params_geometry(int n, const lbm_params *p, std::vector<double> &geo) {
@@ -543,7 +621,7 @@ int lbm_surrogate_get_stats(lbm_surrogate_t s, double *xmu, double *xsd, double 
   return LBM_OK;
 }
 
-int lbm_surrogate_describe(int n, const lbm_params *p, double *feat, double *r_open) {
+int lbm_surrogate_describe(int n, const lbm_params *p, double *feat, double *r_msp) {
   if (n < 0 || (n > 0 && (!p || !feat))) {
     set_err("lbm_surrogate_describe: bad arguments");
     return LBM_EINVAL;
@@ -551,8 +629,8 @@ int lbm_surrogate_describe(int n, const lbm_params *p, double *feat, double *r_o
   if (n == 0) return LBM_OK;
   std::vector<double> geo;
   SGTRY(params_geometry(n, p, geo));
-  if (r_open)
-    for (int t = 0; t < n; ++t) r_open[t] = opening_radius(geo.data() + (size_t)t * 19);
+  if (r_msp)
+    for (int t = 0; t < n; ++t) r_msp[t] = msp_radius(geo.data() + (size_t)t * 19);
   hipStream_t st = (hipStream_t)p[0].stream;
   double *geo_d = nullptr, *feat_d = nullptr;
   SGTRY(dalloc(&geo_d, geo.size()));
@@ -915,13 +993,14 @@ int lbm_surrogate_pce(lbm_surrogate_t s, int n, const lbm_params *p, const doubl
 
   std::vector<int> fb;
   for (int t = 0; t < n; ++t) {
-    const double r_open = opening_radius(geo.data() + (size_t)t * 19);
+    const double r_msp = msp_radius(geo.data() + (size_t)t * 19);
     const double m0 = mean[(size_t)t * sg::kOut], s0 = sd[(size_t)t * sg::kOut];
-    pce[t] = r_open > 0 ? m0 / r_open : NAN;
-    pce_std[t] = r_open > 0 ? s0 / r_open : NAN;
+    pce[t] = r_msp > 0 ? m0 / r_msp : NAN;
+    pce_std[t] = r_msp > 0 ? s0 / r_msp : NAN;
     for (int j = 0; j < LBM_SG_NCURVE; ++j)
       curve[(size_t)t * LBM_SG_NCURVE + j] = mean[(size_t)t * sg::kOut + 1 + j];
-    const bool disagree = !(s0 <= threshold * std::fabs(m0));
+    // (no MS-P radius: no network answer, the LBM decides)
+    const bool disagree = !(s0 <= threshold * std::fabs(m0)) || !(r_msp > 0);
     used_fallback[t] = 0;
     if (disagree && run_fallback) fb.push_back(t);
   }

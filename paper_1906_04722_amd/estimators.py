@@ -49,6 +49,38 @@ def msp_radius(R):
                   1e-6 * R, incircle_radius(R), xtol=1e-14 * R)
 
 
+def opening_radius(circles):
+    """Radius of the circle tangent from outside to three circles [(x, y, R)]
+    in their gap (the throat opening; the incircle estimate's radius): the
+    tangency conditions |c - C_i| = r + R_i subtracted pairwise make the
+    centre linear in r, and the first condition leaves a quadratic whose
+    smallest positive root is the gap circle.  NaN if there is none."""
+    C = [(float(c[0]), float(c[1])) for c in circles]
+    R = [float(c[2]) for c in circles]
+    A, b, d = [], [], []
+    for i in (1, 2):
+        A.append((2.0 * (C[0][0] - C[i][0]), 2.0 * (C[0][1] - C[i][1])))
+        b.append(R[i] ** 2 - R[0] ** 2 - (C[i][0] ** 2 + C[i][1] ** 2) + (C[0][0] ** 2 + C[0][1] ** 2))
+        d.append(2.0 * (R[i] - R[0]))
+    det = A[0][0] * A[1][1] - A[0][1] * A[1][0]
+    if det == 0.0:
+        return float("nan")
+    u = ((A[1][1] * b[0] - A[0][1] * b[1]) / det, (A[0][0] * b[1] - A[1][0] * b[0]) / det)
+    v = ((A[1][1] * d[0] - A[0][1] * d[1]) / det, (A[0][0] * d[1] - A[1][0] * d[0]) / det)
+    w = (u[0] - C[0][0], u[1] - C[0][1])
+    qa = v[0] ** 2 + v[1] ** 2 - 1.0
+    qb = 2.0 * (w[0] * v[0] + w[1] * v[1] - R[0])
+    qc = w[0] ** 2 + w[1] ** 2 - R[0] ** 2
+    if abs(qa) < 1e-14:
+        roots = [-qc / qb] if qb != 0.0 else []
+    else:
+        disc = qb * qb - 4.0 * qa * qc
+        roots = [] if disc < 0 else [(-qb - math.sqrt(disc)) / (2.0 * qa),
+                                     (-qb + math.sqrt(disc)) / (2.0 * qa)]
+    pos = [r for r in roots if r > 0]
+    return min(pos) if pos else float("nan")
+
+
 def pc_star(pc, R, gamma):
     """The paper's normalised capillary pressure p_c* = 2 p_c R / gamma."""
     return 2.0 * pc * R / gamma

@@ -90,18 +90,19 @@ def _params_array(probs, stream=None):
     return P, keep
 
 
-def describe(probs, with_opening=False):
+def describe(probs, with_scale=False):
     """Descriptors [n][80] of four-sphere throat problems (on the GPU), and
-    with with_opening=True also the opening radii [n] in lattice units."""
+    with with_scale=True also the targets' scale [n]: the MS-P corner-meniscus
+    radius at entry in lattice units (NaN where there is none)."""
     n = len(probs)
     out = np.zeros((n, NFEAT))
-    r_open = np.zeros(n)
+    r_msp = np.zeros(n)
     if n > 0:
         P, keep = _params_array(probs)
-        lbm._check(lib().lbm_surrogate_describe(n, P, _d(out), _d(r_open)),
+        lbm._check(lib().lbm_surrogate_describe(n, P, _d(out), _d(r_msp)),
                    "lbm_surrogate_describe")
         del keep
-    return (out, r_open) if with_opening else out
+    return (out, r_msp) if with_scale else out
 
 
 class Surrogate:
@@ -218,13 +219,14 @@ class Surrogate:
 def training_set(probs, drains):
     """Descriptors and targets of drained throats (lbm_drain_batch results):
     features [m][80] from the GPU descriptor, targets [m][17] = (p_c^e times
-    the opening radius, the 16 ramp saturations), and the mask of the throats
-    kept (those whose ramp found the entry pressure)."""
-    F, r_open = describe(probs, with_opening=True)
+    the MS-P radius, the 16 ramp saturations), and the mask of the throats
+    kept (those whose ramp found the entry pressure and that have an MS-P
+    radius)."""
+    F, r_msp = describe(probs, with_scale=True)
     pce = np.array([d["pce"] for d in drains], dtype=np.float64)
     S = np.stack([np.asarray(d["S"], dtype=np.float64) for d in drains])
     if S.shape[1] != NCURVE:
         raise ValueError(f"the surrogate's curve has {NCURVE} points, the drains {S.shape[1]}")
-    ok = np.isfinite(pce) & (r_open > 0)
-    T = np.column_stack([pce * r_open, S])
+    ok = np.isfinite(pce) & (r_msp > 0)
+    T = np.column_stack([pce * r_msp, S])
     return F[ok], T[ok], ok

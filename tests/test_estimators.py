@@ -182,3 +182,22 @@ def test_general_msp_root(circles, rs):
     r = est.msp_general_radius(circles)
     An, L, ok = est.msp_general_parts(circles, r)
     assert ok and abs(An - r * L) < 1e-12
+
+
+def test_opening_radius_is_the_gap_circle():
+    """The closed-form opening radius (the incircle estimate's radius, a
+    no-network baseline): the equal-touching case, and general triples
+    against the oracle's root finder on the three tangency conditions."""
+    import oracle.mlp as mlp
+    equal = [(0.0, 0.0, 1.0), (2.0, 0.0, 1.0), (1.0, math.sqrt(3.0), 1.0)]
+    assert est.opening_radius(equal) == pytest.approx(2.0 / math.sqrt(3.0) - 1.0, rel=1e-13)
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        R = rng.uniform(0.8, 1.2, 3)
+        ang = np.array([0.0, 2.0 * np.pi / 3, 4.0 * np.pi / 3]) + rng.uniform(-0.1, 0.1, 3)
+        rad = rng.uniform(1.8, 2.4, 3) / math.sqrt(3.0)
+        circles = [(rad[i] * math.cos(ang[i]), rad[i] * math.sin(ang[i]), R[i]) for i in range(3)]
+        spheres = [(c[0], c[1], 0.0, c[2]) for c in circles]
+        r_ref = mlp.opening_radius(spheres)
+        r = est.opening_radius(circles)
+        assert abs(r - r_ref) <= 1e-9 * r_ref, (circles, r, r_ref)
