@@ -125,7 +125,8 @@ int lbm_surrogate_predict(lbm_surrogate_t m, int n, const double *feat, double *
  * of output 0 exceeds threshold * |mean| (and run_fallback is 1) drain the
  * throat with lbm_drain_batch over pc (host [n][n_pc], n_pc = 16) and c, and
  * take its result.  The network's p_c^e is output 0 divided by r_msp; a
- * throat without an MS-P radius is always drained by the LBM.
+ * throat without an MS-P radius counts as disagreeing (drained by the LBM
+ * when run_fallback is 1, NaN otherwise).
  * pce [n], curve [n][16], pce_std [n] (ensemble std of p_c^e; 0 where the
  * LBM answered), used_fallback [n] (0/1) are host outputs; info may be NULL.
  * Returns the fallback batch's warning code if any. */
