@@ -407,6 +407,9 @@ double msp_radius(const double *G) {
     S.R[i] = G[4 * i + 3];
     scale = std::max(scale, S.R[i]);
   }
+  // (the scan starts at a positive radius and ends above 10x the scale, so
+  // it needs a positive, finite scale to terminate)
+  if (!(scale > 0.0 && scale < INFINITY)) return NAN;
   auto f = [&](double r) {
     double An, L;
     msp_parts(S, r, An, L);
@@ -449,6 +452,12 @@ int params_geometry(int n, const lbm_params *p, std::vector<double> &geo) {
     double *G = geo.data() + (size_t)t * 19;
     for (int i = 0; i < 4; ++i) {
       const lbm_sphere &sp = q.spheres[ids[i]];
+      if (!(std::isfinite(sp.c[0]) && std::isfinite(sp.c[1]) && std::isfinite(sp.c[2]) &&
+            std::isfinite(sp.r) && sp.r > 0)) {
+        set_err("throat %d: sphere %d has a non-finite centre or a non-positive radius", t,
+                ids[i]);
+        return LBM_EINVAL;
+      }
       G[4 * i + 0] = sp.c[0];
       G[4 * i + 1] = sp.c[1];
       G[4 * i + 2] = sp.c[2];

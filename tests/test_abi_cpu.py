@@ -49,6 +49,19 @@ def test_surrogate_arguments_rejected_without_gpu_work():
     assert L.lbm_surrogate_predict(None, 1, None, None, None) == lbm.LBM_EINVAL
     assert L.lbm_surrogate_members(None) == 0
     L.lbm_surrogate_free(None)
+    # a throat sphere of zero radius is refused before any device work (the
+    # MS-P scale of the targets needs positive radii)
+    import numpy as np
+    import synth
+    pr = synth.c1_problem()
+    pr.spheres = np.array(pr.spheres, dtype=np.float64)
+    pr.spheres[pr.prism_ids[0], 3] = 0.0
+    P, keep = surrogate._params_array([pr])
+    feat = np.zeros((1, surrogate.NFEAT))
+    r = np.zeros(1)
+    assert L.lbm_surrogate_describe(1, P, surrogate._d(feat), surrogate._d(r)) == lbm.LBM_EINVAL
+    assert b"radius" in L.lbm_last_error()
+    del keep
 
 
 def test_invalid_arguments_rejected_without_gpu_work():
