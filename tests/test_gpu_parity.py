@@ -162,11 +162,13 @@ def test_closed_box_mass_drift_fp32():
     assert drift.max() < 1e-5
 
 
-def test_autotune_keeps_state_and_results():
-    """The autotuner's trial launches leave the state untouched, and the
-    schedule it picks gives bit-identical results."""
+@pytest.mark.parametrize("maker", [_ragged_problem, _periodic_problem])
+def test_autotune_keeps_state_and_results(maker):
+    """The autotuner's trials (real steps from a saved copy of the state,
+    ghost planes included on the z-periodic box) leave the state untouched,
+    and the schedule it picks gives bit-identical results."""
     lbm = _lbm()
-    p = _ragged_problem()
+    p = maker()
     a = lbm.Throat(p)
     a.step(10)
     f0 = a.f()
