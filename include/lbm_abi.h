@@ -169,6 +169,18 @@ int lbm_get_populations(lbm_throat_t h, double *f);
  * imposed values, solid nodes zero. Synchronous. */
 int lbm_get_density(lbm_throat_t h, double *rho);
 
+/* The same read-back as lbm_get_density, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): it calls no hipMalloc, hipFree or other allocating
+ * routine.  The densities are staged in a fixed device array of 2^21 nodes x
+ * 2 doubles (32 MiB, a 128^3 box), which each GPU the library runs on holds
+ * from the first call until the process ends.  Boxes of more than 2^21 nodes
+ * are refused with LBM_EINVAL (output untouched).  Every call on one GPU
+ * stages through that GPU's one array: calls that overlap on one GPU (handles
+ * on different streams or host threads) race and must be serialised by the
+ * caller.  Synchronous on the handle's stream. */
+int lbm_get_density_noalloc(lbm_throat_t h, double *rho);
+
 /* FP64 reductions over fluid nodes: masses [2] (Eq. 2 summed) and the
  * wetting saturation S_w = mean of (phi + phi_b) / (2 phi_b) with
  * phi = (rho_w - rho_nw)/(rho_w + rho_nw), phi_b = (rho_major - rho_minor) /

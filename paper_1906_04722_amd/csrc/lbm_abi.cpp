@@ -696,6 +696,36 @@ int lbm_get_density(lbm_throat_t h, double *rho) {
   return LBM_OK;
 }
 
+int lbm_get_density_noalloc(lbm_throat_t h, double *rho) {
+  if (!h || !rho) {
+    set_err("lbm_get_density_noalloc: NULL argument");
+    return LBM_EINVAL;
+  }
+  if (h->N > sc::kScratchNodes) {
+    set_err("lbm_get_density_noalloc: %zu nodes exceed the fixed staging array of %zu nodes",
+            h->N, sc::kScratchNodes);
+    return LBM_EINVAL;
+  }
+  double *stage = nullptr;
+  hipError_t e = sc::scratch_address(&stage);
+  if (e != hipSuccess) {
+    set_err("lbm_get_density_noalloc: no address for the staging array: %s",
+            hipGetErrorString(e));
+    return LBM_EHIP;
+  }
+  // k_density writes all 2 N values, so nothing left by an earlier call is read
+  const sc::Dom d = dom(h, h->g[h->cur], nullptr);
+  e = sc::launch_density(d, h->P, h->rres_d, stage, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(rho, stage, sizeof(double) * 2 * h->N, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    set_err("lbm_get_density_noalloc: read-back failed: %s", hipGetErrorString(e));
+    return LBM_EHIP;
+  }
+  return LBM_OK;
+}
+
 int lbm_reduce(lbm_throat_t h, double *mass2, double *S_w) {
   if (!h) {
     set_err("NULL handle");

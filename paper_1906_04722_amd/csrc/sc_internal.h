@@ -156,6 +156,13 @@ hipError_t launch_export(const Dom &d, const Phys &P, const double *rres_d, doub
                          hipStream_t st);
 hipError_t launch_density(const Dom &d, const Phys &P, const double *rres_d, double *rho,
                           hipStream_t st);
+// fixed device staging array of the allocation-free density read-back:
+// kScratchDoubles doubles (32 MiB), enough for 2 densities of 2^21 nodes (a
+// 128^3 box).  scratch_address gives the device address of the current
+// device's copy (looked up once per device, then cached).
+constexpr size_t kScratchNodes = (size_t)1 << 21;
+constexpr size_t kScratchDoubles = 2 * kScratchNodes;
+hipError_t scratch_address(double **out);
 // chunked FP64 reduction over subdomains: each reduction chunk is a range of
 // kRedEntries entries of one subdomain's node list; per chunk the partial
 // sums of rho_w, rho_nw and the saturation term over its fluid nodes, then

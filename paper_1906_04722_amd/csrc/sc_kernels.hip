@@ -14,6 +14,7 @@
 // the store of the post-collision state.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "geom.h"
 #include "sc_internal.h"
@@ -961,6 +962,33 @@ hipError_t launch_density(const Dom &d, const Phys &P, const double *rres_d, dou
   const unsigned blocks = (unsigned)std::min<size_t>((d.N + 255) / 256, 65536);
   hipLaunchKernelGGL(k_density, dim3(blocks), dim3(256), 0, st, d, P, rres_d, rho);
   return hipGetLastError();
+}
+
+// ---- fixed staging array of the allocation-free density read-back ---------
+// A file-scope device array, one copy per device for the life of the process.
+// Host code never uses its name as an address (on the host the name is only a
+// stand-in for the symbol): the device address of the current device's copy
+// comes from hipGetSymbolAddress, taken once per device and kept.
+static __device__ __align__(256) __attribute__((used)) double scratch[kScratchDoubles];
+
+hipError_t scratch_address(double **out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double *addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = (double *)p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 // ---- FP64 reductions ------------------------------------------------------

@@ -74,6 +74,7 @@ SIGNATURES = {
     "lbm_get_types": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_ubyte)]),
     "lbm_get_populations": (ctypes.c_int, [ctypes.c_void_p, _dp]),
     "lbm_get_density": (ctypes.c_int, [ctypes.c_void_p, _dp]),
+    "lbm_get_density_noalloc": (ctypes.c_int, [ctypes.c_void_p, _dp]),
     "lbm_reduce": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp]),
     "lbm_probe_invaded": (ctypes.c_int, [ctypes.c_void_p, _ip]),
     "lbm_drain_throat": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_int,
@@ -207,6 +208,12 @@ class Throat:
     def density(self):
         a = np.zeros(2 * self.N)
         _check(lib().lbm_get_density(self.h, _dptr(a)), "lbm_get_density")
+        return a.reshape((2,) + self.shape)
+
+    def density_noalloc(self):
+        """Densities through the allocation-free read-back (fixed staging array)."""
+        a = np.zeros(2 * self.N)
+        _check(lib().lbm_get_density_noalloc(self.h, _dptr(a)), "lbm_get_density_noalloc")
         return a.reshape((2,) + self.shape)
 
     def reduce(self):
