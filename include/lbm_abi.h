@@ -54,6 +54,7 @@ extern "C" {
 #define LBM_EHIP (-3)       /* a HIP runtime call failed                    */
 #define LBM_ENONFINITE (-4) /* the state became non-finite                  */
 #define LBM_ESTATE (-5)     /* call not valid in the handle's state         */
+#define LBM_EIO (-6)        /* a checkpoint file could not be written/read  */
 #define LBM_WNOTCONV 1      /* a ramp point hit its step cap, or bisection
                                its run limit                                */
 #define LBM_WPARTIAL 2      /* batch: some subdomains failed (see status)  */
@@ -73,6 +74,7 @@ extern "C" {
 #define LBM_PT_CONVERGED 0
 #define LBM_PT_NOT_CONVERGED 1
 #define LBM_PT_NONFINITE 2
+#define LBM_PT_NOT_RUN 3    /* batch: the point was never reached        */
 
 typedef struct {
   double c[3]; /* centre, lattice units */
@@ -123,9 +125,25 @@ typedef struct {
   double *S;           /* [n_pc] wetting saturation at the end of each point */
   long long *steps;    /* [n_pc] steps used by each point                   */
   int *status;         /* [n_pc] LBM_PT_*                                   */
+  int failed;          /* 1: the state became non-finite (batch only; a
+                          single drain returns LBM_ENONFINITE instead): the
+                          failing point and every later one carry
+                          LBM_PT_NONFINITE and pce, pce_lo, pce_hi are NaN */
 } lbm_drain_result;
 
 typedef struct lbm_throat *lbm_throat_t;
+
+/* Device-memory budget of the library's allocating calls, for callers that
+ * share the GPU: with bytes > 0, lbm_throat_init, lbm_drain_throat and
+ * lbm_drain_batch compute the device memory a call needs before allocating
+ * anything (per subdomain: two population buffers of 152 bytes per padded
+ * node, plus 25 bytes per node of masks, classes, densities and the node
+ * list; two more population buffers for the ramp checkpoints of a drain) and
+ * refuse a call that needs more than `bytes` with LBM_ENOMEM, having
+ * allocated nothing.  0 (the default) sets no budget; calls are then refused
+ * only when the device reports less free memory than they need.  Process
+ * wide; takes effect for calls that start after it returns. */
+int lbm_set_memory_budget(size_t bytes);
 
 /* Create a subdomain: voxelize the geometry on the device, allocate two FP32
  * population buffers (2 x 152 bytes per node, nx and ny padded to multiples
@@ -196,12 +214,49 @@ int lbm_probe_invaded(lbm_throat_t h, int *invaded);
  * first invaded point, bisect between the last stable state and pc[i] on a
  * copy of the state until the bracket is within c->bisect_rel; the entry
  * pressure is reported as that bracket (Sec. 2.2.2: p_c^e is the maximum p_c
- * reached before invasion).  Bisection stops after 40 runs: a throat
- * already invaded at pc[0] brackets from 0, where the relative width may
- * never shrink; its bracket is then reported as reached.  Synchronous.
- * Returns LBM_WNOTCONV if a point hit its cap or bisection its run limit. */
+ * reached before invasion).  pc[0] must be > 0.  Bisection stops after 40
+ * runs: a throat already invaded at pc[0] brackets from 0, where the
+ * relative width may never shrink; its bracket is then reported as reached.
+ * Synchronous.  Returns LBM_WNOTCONV if a point hit its cap or bisection its
+ * run limit, LBM_ENONFINITE (outputs untouched) if the state became
+ * non-finite. */
 int lbm_drain_throat(lbm_throat_t h, const double *pc, int n_pc, const lbm_conv *c,
                      lbm_drain_result *out);
+
+/* The same drainage ramp in resumable form.  lbm_drain_begin validates as
+ * lbm_drain_throat does, keeps pc and c in the handle and starts the first
+ * point; lbm_drain_advance runs it in whole chunks of c->check_every steps
+ * until it ends or max_steps (>= 0) lattice steps have run in this call
+ * (*done = 1 once the ramp has ended; done may be NULL); lbm_drain_get
+ * copies the results so far into out, whose arrays hold n_pc entries (n_pc
+ * must equal the ramp's; points not reached yet carry LBM_PT_NOT_RUN), and
+ * sets *done.  Begin + advance to the end + get gives
+ * lbm_drain_throat's results bit for bit, however the steps are split
+ * between calls and whether or not the handle was saved and loaded between
+ * them.  A non-finite state ends the ramp with LBM_ENONFINITE (lbm_drain_get
+ * then reports failed = 1).  lbm_drain_advance and lbm_drain_get return
+ * LBM_ESTATE on a handle with no ramp begun; all three are synchronous. */
+int lbm_drain_begin(lbm_throat_t h, const double *pc, int n_pc, const lbm_conv *c);
+int lbm_drain_advance(lbm_throat_t h, long long max_steps, int *done);
+int lbm_drain_get(lbm_throat_t h, int n_pc, lbm_drain_result *out, int *done);
+
+/* Checkpoint and resume (Sec. 2.2.2's ramp is a long sequence of steady
+ * states).  lbm_save writes to the file at `path` (host byte order): the
+ * subdomain's size, a hash of its node classes and its parameters; the inlet
+ * density and the step count; the state of a ramp begun with
+ * lbm_drain_begin (point, bracket, results so far, the run in progress);
+ * the current populations (FP32, 152 bytes per padded node, ghost planes
+ * included) and, while a ramp is running, its two checkpoints.
+ * lbm_load reads such a file into a handle created with the same statement
+ * (lbm_params; the file is refused with LBM_EINVAL, handle untouched, when
+ * size, node classes or parameters differ) and restores all of it: stepping
+ * or advancing the ramp then continues bit for bit as in the handle that was
+ * saved.  Errors: LBM_EIO when the file cannot be opened, written or read
+ * (a load that fails while reading the populations leaves the handle's
+ * state undefined: load again or free it), LBM_ENOMEM, LBM_EHIP.
+ * Synchronous. */
+int lbm_save(lbm_throat_t h, const char *path);
+int lbm_load(lbm_throat_t h, const char *path);
 
 /* Summary of a batched drainage (optional output of lbm_drain_batch). */
 typedef struct {
@@ -216,7 +271,7 @@ typedef struct {
 
 /* Batched drainage of n subdomains (Sec. 2.2.2: the throats are solved
  * independently): p[t] states subdomain t (each needs a probe node), pc is
- * host [n][n_pc] (each row strictly increasing), out[t] receives the same
+ * host [n][n_pc] (each row positive and strictly increasing), out[t] receives the same
  * results as lbm_drain_throat would (bit for bit: the same kernels and the
  * same reduction order).  One fused-step launch covers the live tiles of all
  * running subdomains; the ramp and bisection decisions are taken on the
@@ -226,8 +281,9 @@ typedef struct {
  * (two buffers and two ramp checkpoints) plus what lbm_throat_init holds per
  * subdomain.  Synchronous.  Returns
  * LBM_WNOTCONV if a point hit its cap, LBM_WPARTIAL if a subdomain became
- * non-finite (its points carry LBM_PT_NONFINITE; the others are complete).
- * info may be NULL. */
+ * non-finite: its result has failed = 1, NaN entry pressures and
+ * LBM_PT_NONFINITE from the failing point on; the other subdomains are
+ * complete and equal their single drains.  info may be NULL. */
 int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, const lbm_conv *c,
                     lbm_drain_result *out, lbm_batch_info *info);
 

@@ -128,7 +128,9 @@ int lbm_surrogate_predict(lbm_surrogate_t m, int n, const double *feat, double *
  * throat without an MS-P radius counts as disagreeing (drained by the LBM
  * when run_fallback is 1, NaN otherwise).
  * pce [n], curve [n][16], pce_std [n] (ensemble std of p_c^e; 0 where the
- * LBM answered), used_fallback [n] (0/1) are host outputs; info may be NULL.
+ * LBM answered), used_fallback [n] are host outputs: 0 network answer, 1 LBM
+ * answer, 2 the LBM drain of the throat became non-finite (pce and pce_std
+ * NaN; the call then returns LBM_WPARTIAL); info may be NULL.
  * Returns the fallback batch's warning code if any. */
 int lbm_surrogate_pce(lbm_surrogate_t m, int n, const lbm_params *p, const double *pc, int n_pc,
                       const lbm_conv *c, double threshold, int run_fallback, double *pce,

@@ -613,7 +613,7 @@ int orc_drain(orc_sim *s, const double *pc, int n_pc, double tol, int every, lon
   if (!s || !pc || n_pc < 1 || !S || !steps || !status || !pce3 || !invaded_at) return -1;
   if (!(tol > 0) || every < 1 || cap < every || !(bisect_rel > 0) || s->probe < 0) return -1;
   for (int i = 0; i < n_pc; ++i)
-    if (!isfinite(pc[i]) || !(orc_rho_in_for_pc(s, pc[i]) > 0)) return -1;
+    if (!isfinite(pc[i]) || !(pc[i] > 0) || !(orc_rho_in_for_pc(s, pc[i]) > 0)) return -1;
   for (int i = 1; i < n_pc; ++i)
     if (!(pc[i] > pc[i - 1])) return -1;
 

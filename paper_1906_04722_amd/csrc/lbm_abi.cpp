@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -18,6 +20,7 @@
 
 namespace {
 thread_local std::string g_err;
+std::atomic<unsigned long long> g_budget{0};  // bytes; 0 = no budget
 }  // namespace
 
 namespace lbmh {
@@ -28,6 +31,21 @@ void set_err(const char *fmt, ...) {
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
   g_err = buf;
+}
+
+size_t subdomain_bytes(int nx, int ny, int nz, bool checkpoints) {
+  const size_t pop = sizeof(float) * sc::pop_elems(nx, ny, nz);
+  const size_t N = (size_t)nx * ny * nz;
+  return (checkpoints ? 4 : 2) * pop + 25 * N + ((size_t)1 << 20);
+}
+
+int check_budget(size_t need, const char *what) {
+  const unsigned long long b = g_budget.load();
+  if (b && need > b) {
+    set_err("%s needs %zu bytes of device memory, over the budget of %llu bytes", what, need, b);
+    return LBM_ENOMEM;
+  }
+  return LBM_OK;
 }
 }  // namespace lbmh
 
@@ -340,6 +358,11 @@ extern "C" {
 
 const char *lbm_last_error(void) { return g_err.c_str(); }
 
+int lbm_set_memory_budget(size_t bytes) {
+  g_budget.store(bytes);
+  return LBM_OK;
+}
+
 int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
   g_err.clear();
   if (!out) {
@@ -347,6 +370,7 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
     return LBM_EINVAL;
   }
   TRY(validate(p));
+  TRY(lbmh::check_budget(lbmh::subdomain_bytes(p->nx, p->ny, p->nz, false), "lbm_throat_init"));
   lbm_throat *h = new (std::nothrow) lbm_throat();
   if (!h) {
     set_err("host allocation failed");
@@ -554,10 +578,10 @@ int lbm_throat_init(const lbm_params *p, lbm_throat_t *out) {
     // read and write whole lines of the population buffers
     const size_t nxy = (size_t)h->nx * h->ny;
     for (int z = 0; z < h->nz; ++z)
-      for (int by = 0; by < h->ny; by += sc::kBY)
-        for (int bx = 0; bx < h->nx; bx += sc::kBX)
-          for (int y = by; y < std::min(by + sc::kBY, h->ny); ++y)
-            for (int x = bx; x < std::min(bx + sc::kBX, h->nx); ++x) {
+      for (int by = -sc::kOY; by < h->ny; by += sc::kBY)
+        for (int bx = -sc::kOX; bx < h->nx; bx += sc::kBX)
+          for (int y = std::max(by, 0); y < std::min(by + sc::kBY, h->ny); ++y)
+            for (int x = std::max(bx, 0); x < std::min(bx + sc::kBX, h->nx); ++x) {
               const size_t n = (size_t)z * nxy + (size_t)y * h->nx + x;
               if (h->types[n] != sc::kSolid) list.push_back((uint32_t)n);
             }
@@ -756,28 +780,47 @@ int lbm_probe_invaded(lbm_throat_t h, int *invaded) {
   return LBM_OK;
 }
 
-int lbm_drain_throat(lbm_throat_t h, const double *pc, int n_pc, const lbm_conv *c,
-                     lbm_drain_result *out) {
-  if (!h || !pc || n_pc < 1 || !c || !out || !out->S || !out->steps || !out->status) {
-    set_err("lbm_drain_throat: NULL argument or n_pc < 1");
+}  // extern "C"
+
+namespace {
+
+// ---- the drainage ramp of one subdomain as a resumable state machine -----
+// Sec. 2.2.2: the capillary pressures are visited in increasing order, each
+// held until the wetting saturation settles; the first invaded interval is
+// bisected from the last stable state.  The machine advances in chunks of
+// check_every steps, so a caller can stop it after any chunk, save the
+// handle (lbm_save) and resume it in another handle (lbm_load); run to the
+// end in one call it is lbm_drain_throat.
+
+int check_drain_args(lbm_throat *h, const double *pc, int n_pc, const lbm_conv *c,
+                     const char *who) {
+  if (!h || !pc || n_pc < 1 || !c) {
+    set_err("%s: NULL argument or n_pc < 1", who);
     return LBM_EINVAL;
   }
   if (!(c->tol > 0) || c->check_every < 1 || c->max_steps < c->check_every ||
       !(c->bisect_rel > 0)) {
-    set_err("lbm_drain_throat: invalid convergence settings");
+    set_err("%s: invalid convergence settings", who);
     return LBM_EINVAL;
   }
   if (h->probe < 0) {
-    set_err("lbm_drain_throat needs a probe node");
+    set_err("%s needs a probe node", who);
     return LBM_ESTATE;
   }
   for (int i = 0; i < n_pc; ++i) {
-    if (!std::isfinite(pc[i]) || !(lbm_rho_in_for_pc(h, pc[i]) > 0) ||
+    if (!std::isfinite(pc[i]) || !(pc[i] > 0) || !(lbm_rho_in_for_pc(h, pc[i]) > 0) ||
         (i > 0 && !(pc[i] > pc[i - 1]))) {
-      set_err("pc must be finite, strictly increasing and give a positive inlet density");
+      set_err("%s: pc must be finite, positive, strictly increasing and give a positive inlet "
+              "density", who);
       return LBM_EINVAL;
     }
   }
+  return LBM_OK;
+}
+
+int ensure_checkpoints(lbm_throat *h, const char *who) {
+  if (!h->save[0] || !h->save[1])
+    TRY(lbmh::check_budget(lbmh::subdomain_bytes(h->nx, h->ny, h->nz, true), who));
   for (int i = 0; i < 2; ++i)
     if (!h->save[i] &&
         hipMalloc((void **)&h->save[i], sizeof(float) * sc::pop_elems(h->nx, h->ny, h->nz)) !=
@@ -785,93 +828,463 @@ int lbm_drain_throat(lbm_throat_t h, const double *pc, int n_pc, const lbm_conv 
       set_err("hipMalloc of a ramp checkpoint failed");
       return LBM_ENOMEM;
     }
-  float *stable = h->save[0], *mainsave = h->save[1];
-  std::vector<double> S(n_pc);
-  std::vector<long long> steps(n_pc);
-  std::vector<int> status(n_pc);
-  TRY(copy_state(h, stable, h->g[h->cur]));
-  double stable_pc = 0.0, stable_rho_in = h->rho_in;
-  int inv_at = -1, n_bis = 0;
-  double lo = NAN, hi = NAN;
-  long long total = 0;
-  bool warn = false;
-  for (int i = 0; i < n_pc; ++i) {
-    TRY(set_rho_in(h, lbm_rho_in_for_pc(h, pc[i])));
-    int inv = 0;
-    const int st = run_to_steady(h, c, &S[i], &steps[i], &inv);
-    if (st < 0) return st;
-    status[i] = st;
-    total += steps[i];
+  return LBM_OK;
+}
+
+// a run to steady state starts: the saturation it is compared against
+int run_start(lbm_throat *h) {
+  double r[5];
+  TRY(reduce_now(h, r));
+  h->ramp.S_old = r[2];
+  h->ramp.run_steps = 0;
+  return LBM_OK;
+}
+
+// one chunk of check_every steps of the run in progress; *ended = 1 when the
+// run has ended, with its status, saturation and invasion test
+int run_chunk(lbm_throat *h, int *ended, int *st, double *S, int *inv) {
+  HostRamp &R = h->ramp;
+  double r[5];
+  if (h->timing) HIPCHK(hipEventRecord(h->tev[0], h->stream));
+  TRY(run_steps(h, R.c.check_every));
+  if (h->timing) HIPCHK(hipEventRecord(h->tev[1], h->stream));
+  R.run_steps += R.c.check_every;
+  TRY(reduce_now(h, r));
+  if (h->timing) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->tev[0], h->tev[1]));
+    h->timed_ms += ms;
+    h->timed_launches += R.c.check_every;
+  }
+  const double S_new = r[2];
+  *ended = 1;
+  if (!std::isfinite(S_new))
+    *st = LBM_PT_NONFINITE;
+  else if (std::fabs(S_new - R.S_old) < R.c.tol)
+    *st = LBM_PT_CONVERGED;
+  else if (R.run_steps >= R.c.max_steps)
+    *st = LBM_PT_NOT_CONVERGED;
+  else
+    *ended = 0;
+  *S = S_new;
+  *inv = r[4] > r[3] ? 1 : 0;
+  if (!*ended) R.S_old = S_new;
+  return LBM_OK;
+}
+
+int ramp_next_point(lbm_throat *h) {
+  HostRamp &R = h->ramp;
+  R.point += 1;
+  if (R.point >= (int)R.pc.size()) {
+    R.phase = HostRamp::kDone;
+    return LBM_OK;
+  }
+  R.phase = HostRamp::kRamp;
+  TRY(set_rho_in(h, lbm_rho_in_for_pc(h, R.pc[R.point])));
+  return run_start(h);
+}
+
+// the next bisection run from the last stable state, or the end of the
+// bisection: back to the invaded ramp state and on to the next point
+int ramp_bisect_or_resume(lbm_throat *h) {
+  HostRamp &R = h->ramp;
+  if ((R.hi - R.lo) / R.hi > R.c.bisect_rel) {
+    if (R.runs < sc::kMaxBisect) {
+      ++R.runs;
+      R.mid = 0.5 * (R.lo + R.hi);
+      R.phase = HostRamp::kBisect;
+      TRY(copy_state(h, h->g[h->cur], h->save[0]));
+      TRY(set_rho_in(h, lbm_rho_in_for_pc(h, R.mid)));
+      return run_start(h);
+    }
+    R.warn = 1;  // bracket left wider than asked (a throat invaded at pc[0])
+  }
+  TRY(copy_state(h, h->g[h->cur], h->save[1]));
+  TRY(set_rho_in(h, R.main_rho_in));
+  return ramp_next_point(h);
+}
+
+int ramp_begin(lbm_throat *h, const double *pc, int n_pc, const lbm_conv *c) {
+  TRY(ensure_checkpoints(h, "lbm_drain"));
+  HostRamp R;
+  R.pc.assign(pc, pc + n_pc);
+  R.c = *c;
+  R.S.assign(n_pc, 0.0);
+  R.steps.assign(n_pc, 0);
+  R.status.assign(n_pc, LBM_PT_NOT_RUN);
+  R.phase = HostRamp::kRamp;
+  R.point = 0;
+  h->ramp = std::move(R);
+  TRY(copy_state(h, h->save[0], h->g[h->cur]));
+  TRY(set_rho_in(h, lbm_rho_in_for_pc(h, h->ramp.pc[0])));
+  return run_start(h);
+}
+
+// advance by whole chunks until the ramp is done or max_steps lattice steps
+// have run in this call
+int ramp_advance(lbm_throat *h, long long max_steps) {
+  HostRamp &R = h->ramp;
+  long long ran = 0;
+  while (R.phase == HostRamp::kRamp || R.phase == HostRamp::kBisect) {
+    if (ran >= max_steps) break;
+    int ended = 0, st = 0, inv = 0;
+    double S = 0.0;
+    TRY(run_chunk(h, &ended, &st, &S, &inv));
+    ran += R.c.check_every;
+    if (!ended) continue;
     if (st == LBM_PT_NONFINITE) {
-      set_err("state became non-finite at ramp point %d", i);
+      set_err("the state became non-finite %s", R.phase == HostRamp::kBisect
+                                                    ? "while bisecting"
+                                                    : "at a ramp point");
+      R.failed = 1;
+      R.phase = HostRamp::kDone;
+      if (R.point < (int)R.status.size() && R.status[R.point] == LBM_PT_NOT_RUN)
+        R.status[R.point] = LBM_PT_NONFINITE;
+      for (size_t j = R.point + 1; j < R.status.size(); ++j) R.status[j] = LBM_PT_NONFINITE;
       return LBM_ENONFINITE;
     }
-    warn |= st == LBM_PT_NOT_CONVERGED;
-    if (!inv) {
-      TRY(copy_state(h, stable, h->g[h->cur]));
-      stable_pc = pc[i];
-      stable_rho_in = h->rho_in;
-      continue;
-    }
-    if (inv_at >= 0) continue;
-    inv_at = i;
-    lo = i == 0 ? 0.0 : stable_pc;
-    hi = pc[i];
-    // bisect on copies of the last stable state; the ramp state is kept aside
-    const double main_rho_in = h->rho_in;
-    TRY(copy_state(h, mainsave, h->g[h->cur]));
-    int runs = 0;
-    while ((hi - lo) / hi > c->bisect_rel) {
-      if (runs == sc::kMaxBisect) {  // bracket left wider than asked (see kMaxBisect)
-        warn = true;
-        break;
-      }
-      ++runs;
-      const double mid = 0.5 * (lo + hi);
-      TRY(copy_state(h, h->g[h->cur], stable));
-      TRY(set_rho_in(h, lbm_rho_in_for_pc(h, mid)));
-      double Sm;
-      long long nm;
-      int invm = 0;
-      const int sm = run_to_steady(h, c, &Sm, &nm, &invm);
-      if (sm < 0) return sm;
-      total += nm;
-      ++n_bis;
-      if (sm == LBM_PT_NONFINITE) {
-        set_err("state became non-finite while bisecting");
-        return LBM_ENONFINITE;
-      }
-      if (invm) {
-        hi = mid;
+    if (R.phase == HostRamp::kRamp) {
+      const int i = R.point;
+      R.S[i] = S;
+      R.steps[i] = R.run_steps;
+      R.status[i] = st;
+      R.total += R.run_steps;
+      R.warn |= st == LBM_PT_NOT_CONVERGED;
+      if (!inv) {
+        TRY(copy_state(h, h->save[0], h->g[h->cur]));
+        R.stable_pc = R.pc[i];
+        TRY(ramp_next_point(h));
+      } else if (R.inv_at >= 0) {
+        TRY(ramp_next_point(h));
       } else {
-        lo = mid;
-        TRY(copy_state(h, stable, h->g[h->cur]));
-        stable_rho_in = h->rho_in;
+        R.inv_at = i;
+        R.lo = i == 0 ? 0.0 : R.stable_pc;
+        R.hi = R.pc[i];
+        R.main_rho_in = h->rho_in;
+        R.runs = 0;
+        TRY(copy_state(h, h->save[1], h->g[h->cur]));
+        TRY(ramp_bisect_or_resume(h));
       }
+    } else {  // a bisection run ended
+      R.total += R.run_steps;
+      ++R.n_bisect;
+      if (inv) {
+        R.hi = R.mid;
+      } else {
+        R.lo = R.mid;
+        TRY(copy_state(h, h->save[0], h->g[h->cur]));
+      }
+      TRY(ramp_bisect_or_resume(h));
     }
-    TRY(copy_state(h, h->g[h->cur], mainsave));
-    TRY(set_rho_in(h, main_rho_in));
   }
-  (void)stable_rho_in;
-  HIPCHK(hipStreamSynchronize(h->stream));
-  for (int i = 0; i < n_pc; ++i) {
-    out->S[i] = S[i];
-    out->steps[i] = steps[i];
-    out->status[i] = status[i];
+  return LBM_OK;
+}
+
+void ramp_result(const lbm_throat *h, lbm_drain_result *out) {
+  const HostRamp &R = h->ramp;
+  const int n = (int)R.pc.size();
+  for (int i = 0; i < n; ++i) {
+    out->S[i] = R.S[i];
+    out->steps[i] = R.steps[i];
+    out->status[i] = R.status[i];
   }
-  out->invaded_at = inv_at;
-  out->n_bisect = n_bis;
-  out->total_steps = total;
-  if (inv_at < 0) {
-    out->pce_lo = pc[n_pc - 1];
+  out->invaded_at = R.inv_at;
+  out->n_bisect = R.n_bisect;
+  out->total_steps = R.total;
+  out->failed = R.failed;
+  if (R.failed) {
+    out->pce_lo = out->pce = out->pce_hi = NAN;
+  } else if (R.inv_at < 0) {
+    out->pce_lo = n ? R.pc[n - 1] : NAN;
     out->pce = NAN;
     out->pce_hi = INFINITY;
   } else {
-    out->pce_lo = lo;
-    out->pce_hi = hi;
-    out->pce = 0.5 * (lo + hi);
+    out->pce_lo = R.lo;
+    out->pce_hi = R.hi;
+    out->pce = 0.5 * (R.lo + R.hi);
   }
-  return warn ? LBM_WNOTCONV : LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_drain_throat(lbm_throat_t h, const double *pc, int n_pc, const lbm_conv *c,
+                     lbm_drain_result *out) {
+  if (!out || !out->S || !out->steps || !out->status) {
+    set_err("lbm_drain_throat: NULL result arrays");
+    return LBM_EINVAL;
+  }
+  TRY(check_drain_args(h, pc, n_pc, c, "lbm_drain_throat"));
+  TRY(ramp_begin(h, pc, n_pc, c));
+  TRY(ramp_advance(h, LLONG_MAX));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  ramp_result(h, out);
+  return h->ramp.warn ? LBM_WNOTCONV : LBM_OK;
+}
+
+int lbm_drain_begin(lbm_throat_t h, const double *pc, int n_pc, const lbm_conv *c) {
+  TRY(check_drain_args(h, pc, n_pc, c, "lbm_drain_begin"));
+  return ramp_begin(h, pc, n_pc, c);
+}
+
+int lbm_drain_advance(lbm_throat_t h, long long max_steps, int *done) {
+  if (!h || max_steps < 0) {
+    set_err("lbm_drain_advance: NULL handle or negative step budget");
+    return LBM_EINVAL;
+  }
+  if (h->ramp.phase == HostRamp::kIdle) {
+    set_err("lbm_drain_advance: no drainage ramp begun on this handle");
+    return LBM_ESTATE;
+  }
+  TRY(ramp_advance(h, max_steps));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (done) *done = h->ramp.phase == HostRamp::kDone ? 1 : 0;
+  return LBM_OK;
+}
+
+int lbm_drain_get(lbm_throat_t h, int n_pc, lbm_drain_result *out, int *done) {
+  if (!h || !out || !out->S || !out->steps || !out->status) {
+    set_err("lbm_drain_get: NULL argument");
+    return LBM_EINVAL;
+  }
+  if (h->ramp.phase == HostRamp::kIdle) {
+    set_err("lbm_drain_get: no drainage ramp begun on this handle");
+    return LBM_ESTATE;
+  }
+  if (n_pc != (int)h->ramp.pc.size()) {
+    set_err("lbm_drain_get: the ramp has %d points, not %d", (int)h->ramp.pc.size(), n_pc);
+    return LBM_EINVAL;
+  }
+  ramp_result(h, out);
+  if (done) *done = h->ramp.phase == HostRamp::kDone ? 1 : 0;
+  return h->ramp.warn ? LBM_WNOTCONV : LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// ---- checkpoint files (lbm_save / lbm_load) --------------------------------
+constexpr char kMagic[8] = {'L', 'B', 'M', 'S', 'C', 'v', '1', '\0'};
+constexpr size_t kIoChunk = (size_t)16 << 20;  // floats per host staging chunk
+
+uint64_t types_hash(const std::vector<uint8_t> &t) {
+  uint64_t x = 1469598103934665603ULL;  // FNV-1a, 64 bit
+  for (uint8_t b : t) {
+    x ^= b;
+    x *= 1099511628211ULL;
+  }
+  return x;
+}
+
+struct File {
+  FILE *f = nullptr;
+  ~File() {
+    if (f) fclose(f);
+  }
+  template <class T>
+  bool put(const T &v) { return fwrite(&v, sizeof(T), 1, f) == 1; }
+  template <class T>
+  bool put_n(const T *v, size_t n) { return n == 0 || fwrite(v, sizeof(T), n, f) == n; }
+  template <class T>
+  bool get(T &v) { return fread(&v, sizeof(T), 1, f) == 1; }
+  template <class T>
+  bool get_n(T *v, size_t n) { return n == 0 || fread(v, sizeof(T), n, f) == n; }
+};
+
+// the fixed part of a subdomain that a saved state must match
+struct Header {
+  char magic[8];
+  int32_t nx, ny, nz, per;
+  uint64_t N, pop_elems, types;
+  double tau[2], G, Gads[2], rho_major, rho_minor, rho_out;
+};
+
+Header header_of(const lbm_throat *h) {
+  Header H;
+  std::memset(&H, 0, sizeof H);
+  std::memcpy(H.magic, kMagic, sizeof kMagic);
+  H.nx = h->nx;
+  H.ny = h->ny;
+  H.nz = h->nz;
+  H.per = h->per;
+  H.N = h->N;
+  H.pop_elems = sc::pop_elems(h->nx, h->ny, h->nz);
+  H.types = types_hash(h->types);
+  H.tau[0] = h->tau[0];
+  H.tau[1] = h->tau[1];
+  H.G = h->G;
+  H.Gads[0] = h->Gads[0];
+  H.Gads[1] = h->Gads[1];
+  H.rho_major = h->rho_major;
+  H.rho_minor = h->rho_minor;
+  H.rho_out = h->rho_out;
+  return H;
+}
+
+bool put_ramp(File &F, const HostRamp &R) {
+  const int32_t n = (int32_t)R.pc.size();
+  bool ok = F.put((int32_t)R.phase) && F.put((int32_t)R.point) && F.put(n) && F.put(R.c.tol) &&
+            F.put((int32_t)R.c.check_every) && F.put((int64_t)R.c.max_steps) &&
+            F.put(R.c.bisect_rel) && F.put((int64_t)R.run_steps) && F.put(R.S_old) &&
+            F.put(R.stable_pc) && F.put(R.lo) && F.put(R.hi) && F.put(R.mid) &&
+            F.put(R.main_rho_in) && F.put((int32_t)R.inv_at) && F.put((int32_t)R.n_bisect) &&
+            F.put((int32_t)R.runs) && F.put((int32_t)R.warn) && F.put((int32_t)R.failed) &&
+            F.put((int64_t)R.total);
+  ok = ok && F.put_n(R.pc.data(), n) && F.put_n(R.S.data(), n);
+  for (int i = 0; ok && i < n; ++i) ok = F.put((int64_t)R.steps[i]) && F.put((int32_t)R.status[i]);
+  return ok;
+}
+
+bool get_ramp(File &F, HostRamp &R) {
+  int32_t phase, point, n, every, inv_at, n_bis, runs, warn, failed;
+  int64_t max_steps, run_steps, total;
+  bool ok = F.get(phase) && F.get(point) && F.get(n) && F.get(R.c.tol) && F.get(every) &&
+            F.get(max_steps) && F.get(R.c.bisect_rel) && F.get(run_steps) && F.get(R.S_old) &&
+            F.get(R.stable_pc) && F.get(R.lo) && F.get(R.hi) && F.get(R.mid) &&
+            F.get(R.main_rho_in) && F.get(inv_at) && F.get(n_bis) && F.get(runs) && F.get(warn) &&
+            F.get(failed) && F.get(total);
+  if (!ok || n < 0 || n > (1 << 24) || phase < HostRamp::kIdle || phase > HostRamp::kDone)
+    return false;
+  R.phase = phase;
+  R.point = point;
+  R.c.check_every = every;
+  R.c.max_steps = max_steps;
+  R.run_steps = run_steps;
+  R.inv_at = inv_at;
+  R.n_bisect = n_bis;
+  R.runs = runs;
+  R.warn = warn;
+  R.failed = failed;
+  R.total = total;
+  R.pc.resize(n);
+  R.S.resize(n);
+  R.steps.resize(n);
+  R.status.resize(n);
+  ok = F.get_n(R.pc.data(), n) && F.get_n(R.S.data(), n);
+  for (int i = 0; ok && i < n; ++i) {
+    int64_t st64;
+    int32_t st32;
+    ok = F.get(st64) && F.get(st32);
+    R.steps[i] = st64;
+    R.status[i] = st32;
+  }
+  return ok && (R.phase == HostRamp::kIdle || (n >= 1 && point >= 0 && point <= n));
+}
+
+// one device buffer of pop_elems floats to or from the file, in chunks
+int buffer_out(lbm_throat *h, File &F, const float *dev, size_t n) {
+  std::vector<float> tmp(std::min(n, kIoChunk));
+  for (size_t o = 0; o < n; o += kIoChunk) {
+    const size_t k = std::min(kIoChunk, n - o);
+    HIPCHK(hipMemcpyAsync(tmp.data(), dev + o, sizeof(float) * k, hipMemcpyDeviceToHost,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (!F.put_n(tmp.data(), k)) {
+      set_err("lbm_save: write failed");
+      return LBM_EIO;
+    }
+  }
+  return LBM_OK;
+}
+
+int buffer_in(lbm_throat *h, File &F, float *dev, size_t n) {
+  std::vector<float> tmp(std::min(n, kIoChunk));
+  for (size_t o = 0; o < n; o += kIoChunk) {
+    const size_t k = std::min(kIoChunk, n - o);
+    if (!F.get_n(tmp.data(), k)) {
+      set_err("lbm_load: the file ends inside a population buffer");
+      return LBM_EIO;
+    }
+    HIPCHK(hipMemcpyAsync(dev + o, tmp.data(), sizeof(float) * k, hipMemcpyHostToDevice,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_save(lbm_throat_t h, const char *path) {
+  if (!h || !path) {
+    set_err("lbm_save: NULL argument");
+    return LBM_EINVAL;
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  File F;
+  F.f = fopen(path, "wb");
+  if (!F.f) {
+    set_err("lbm_save: cannot open %s for writing", path);
+    return LBM_EIO;
+  }
+  const Header H = header_of(h);
+  const bool with_ckpt = h->ramp.phase == HostRamp::kRamp || h->ramp.phase == HostRamp::kBisect;
+  const int32_t nbuf = with_ckpt ? 3 : 1;
+  if (!F.put(H) || !F.put(h->rho_in) || !F.put((int64_t)h->steps_done) || !put_ramp(F, h->ramp) ||
+      !F.put(nbuf)) {
+    set_err("lbm_save: write to %s failed", path);
+    return LBM_EIO;
+  }
+  const size_t n = sc::pop_elems(h->nx, h->ny, h->nz);
+  TRY(buffer_out(h, F, h->g[h->cur], n));
+  if (with_ckpt) {
+    TRY(buffer_out(h, F, h->save[0], n));
+    TRY(buffer_out(h, F, h->save[1], n));
+  }
+  if (fflush(F.f) != 0) {
+    set_err("lbm_save: write to %s failed", path);
+    return LBM_EIO;
+  }
+  return LBM_OK;
+}
+
+int lbm_load(lbm_throat_t h, const char *path) {
+  if (!h || !path) {
+    set_err("lbm_load: NULL argument");
+    return LBM_EINVAL;
+  }
+  File F;
+  F.f = fopen(path, "rb");
+  if (!F.f) {
+    set_err("lbm_load: cannot open %s", path);
+    return LBM_EIO;
+  }
+  Header H{};
+  double rho_in = 0.0;
+  int64_t steps_done = 0;
+  HostRamp R;
+  int32_t nbuf = 0;
+  if (!F.get(H) || std::memcmp(H.magic, kMagic, sizeof kMagic) != 0) {
+    set_err("lbm_load: %s is not a saved subdomain state", path);
+    return LBM_EINVAL;
+  }
+  const Header mine = header_of(h);
+  if (std::memcmp(&H, &mine, sizeof H) != 0) {
+    set_err("lbm_load: %s holds the state of another subdomain (size, node classes or "
+            "parameters differ)", path);
+    return LBM_EINVAL;
+  }
+  if (!F.get(rho_in) || !F.get(steps_done) || !get_ramp(F, R) || !F.get(nbuf) ||
+      !(nbuf == 1 || nbuf == 3) || !finite_pos(rho_in)) {
+    set_err("lbm_load: %s is truncated or corrupt", path);
+    return LBM_EINVAL;
+  }
+  if (nbuf == 3) TRY(ensure_checkpoints(h, "lbm_load"));
+  // from here on the handle's state is overwritten
+  const size_t n = sc::pop_elems(h->nx, h->ny, h->nz);
+  TRY(buffer_in(h, F, h->g[h->cur], n));
+  if (nbuf == 3) {
+    TRY(buffer_in(h, F, h->save[0], n));
+    TRY(buffer_in(h, F, h->save[1], n));
+  }
+  TRY(set_rho_in(h, rho_in));
+  h->steps_done = steps_done;
+  h->ramp = std::move(R);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
 }
 
 int lbm_time_steps(lbm_throat_t h, long long nsteps, double *ms) {

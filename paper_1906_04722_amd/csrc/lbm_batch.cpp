@@ -46,7 +46,8 @@ struct Batch {
   int *status_d = nullptr, *nact_d = nullptr, *nact_h = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};    // autotuner trials
+  hipEvent_t wall[2] = {nullptr, nullptr};  // the whole drain, first to last kernel
   std::vector<sc::Throat> th_h;
   sc::Sched sched{32, 4, 2};
 
@@ -61,6 +62,8 @@ struct Batch {
       if (p) (void)hipFree(p);
     if (nact_h) (void)hipHostFree(nact_h);
     for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto e : wall)
       if (e) (void)hipEventDestroy(e);
     for (auto x : h) lbm_throat_free(x);
     if (stream) (void)hipStreamDestroy(stream);
@@ -225,19 +228,33 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
     }
     for (int i = 0; i < n_pc; ++i) {
       const double v = pc[(size_t)t * n_pc + i];
-      if (!std::isfinite(v) || (i > 0 && !(v > pc[(size_t)t * n_pc + i - 1])) ||
+      if (!std::isfinite(v) || !(v > 0) || (i > 0 && !(v > pc[(size_t)t * n_pc + i - 1])) ||
           !(p[t].rho_out_w + v / (kCs2 * (1.0 + p[t].G * p[t].rho_minor)) > 0)) {
-        set_err("lbm_drain_batch: pc of subdomain %d must be finite, strictly increasing and "
-                "give a positive inlet density", t);
+        set_err("lbm_drain_batch: pc of subdomain %d must be finite, positive, strictly "
+                "increasing and give a positive inlet density", t);
         return LBM_EINVAL;
       }
     }
+  }
+  {
+    // the whole batch's device memory against the budget, before any allocation
+    size_t need = 0;
+    for (int t = 0; t < n; ++t) {
+      if (p[t].nx < 3 || p[t].ny < 3 || p[t].nz < 3) {
+        set_err("lbm_drain_batch: subdomain %d is smaller than 3 nodes on a side", t);
+        return LBM_EINVAL;
+      }
+      need += lbmh::subdomain_bytes(p[t].nx, p[t].ny, p[t].nz, true);
+    }
+    if (int r = lbmh::check_budget(need, "lbm_drain_batch")) return r;
   }
   Batch B;
   B.n = n;
   BCHK(hipStreamCreate(&B.stream));
   BCHK(hipEventCreate(&B.ev[0]));
   BCHK(hipEventCreate(&B.ev[1]));
+  BCHK(hipEventCreate(&B.wall[0]));
+  BCHK(hipEventCreate(&B.wall[1]));
   // subdomains: geometry, initial state, checkpoints
   std::vector<sc::Chunk> chunks, cchunks;
   std::vector<int> first(n), count(n);
@@ -303,7 +320,10 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
   BCHK(hipMemcpy(B.pc_d, pc, sizeof(double) * n * n_pc, hipMemcpyHostToDevice));
   BCHK(hipMemset(B.S_d, 0, sizeof(double) * n * n_pc));
   BCHK(hipMemset(B.steps_d, 0, sizeof(long long) * n * n_pc));
-  BCHK(hipMemset(B.status_d, 0, sizeof(int) * n * n_pc));
+  {
+    const std::vector<int> not_run((size_t)n * n_pc, LBM_PT_NOT_RUN);
+    BCHK(hipMemcpy(B.status_d, not_run.data(), sizeof(int) * n * n_pc, hipMemcpyHostToDevice));
+  }
   {
     std::vector<int> zper;
     for (int t = 0; t < n; ++t)
@@ -318,7 +338,7 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
       BCHK(hipMemcpy(B.zper_d, zper.data(), sizeof(int) * zper.size(), hipMemcpyHostToDevice));
   }
 
-  hipEvent_t w0 = B.ev[0], w1 = B.ev[1];
+  hipEvent_t w0 = B.wall[0], w1 = B.wall[1];
   BCHK(hipEventRecord(w0, B.stream));
   // shared launch shape, then the initial decisions
   if (int r = autotune(B, 6)) return r;
@@ -372,7 +392,12 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
     out[t].invaded_at = R.invaded_at;
     out[t].n_bisect = R.n_bisect;
     out[t].total_steps = R.total_steps;
-    if (R.invaded_at < 0) {
+    out[t].failed = R.failed ? 1 : 0;
+    if (R.failed) {  // no entry pressure from a state that became non-finite
+      out[t].pce_lo = NAN;
+      out[t].pce = NAN;
+      out[t].pce_hi = NAN;
+    } else if (R.invaded_at < 0) {
       out[t].pce_lo = pc[(size_t)t * n_pc + n_pc - 1];
       out[t].pce = NAN;
       out[t].pce_hi = INFINITY;

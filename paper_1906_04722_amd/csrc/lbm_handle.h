@@ -11,6 +11,26 @@
 #include "lbm_abi.h"
 #include "sc_internal.h"
 
+// host-side drainage ramp of one subdomain (Sec. 2.2.2), advanced in chunks
+// of check_every steps so that a caller can stop it, save it and resume it
+struct HostRamp {
+  enum : int { kIdle = 0, kRamp = 1, kBisect = 2, kDone = 3 };
+  int phase = kIdle;
+  std::vector<double> pc;
+  lbm_conv c{};
+  int point = 0;                // ramp point being run (kRamp) or bisected (kBisect)
+  // the run in progress: steps so far and the saturation of the last check
+  long long run_steps = 0;
+  double S_old = 0.0;
+  // bracket of the entry pressure and the states kept for the bisection
+  double stable_pc = 0.0, lo = 0.0, hi = 0.0, mid = 0.0, main_rho_in = 0.0;
+  int inv_at = -1, n_bisect = 0, runs = 0, warn = 0, failed = 0;
+  long long total = 0;
+  std::vector<double> S;
+  std::vector<long long> steps;
+  std::vector<int> status;
+};
+
 struct lbm_throat {
   int nx = 0, ny = 0, nz = 0, per = 0, bc[3] = {0, 0, 0};
   size_t N = 0;
@@ -58,6 +78,7 @@ struct lbm_throat {
   bool timing = false;
   double timed_ms = 0.0;
   long long timed_launches = 0;
+  HostRamp ramp;
 };
 
 
@@ -69,5 +90,9 @@ int sync_desc(lbm_throat *h);
 int rebuild_tiles(lbm_throat *h);
 int set_rho_in(lbm_throat *h, double r);
 int copy_state(lbm_throat *h, float *dst, const float *src);
+// device memory of one subdomain (with or without the two ramp checkpoints)
+// and the refusal of a call whose need exceeds the memory budget
+size_t subdomain_bytes(int nx, int ny, int nz, bool checkpoints);
+int check_budget(size_t need, const char *what);
 
 }  // namespace lbmh

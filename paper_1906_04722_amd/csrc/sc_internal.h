@@ -31,8 +31,15 @@ constexpr int kTypeShift = 24;
 // base address and 32-bit offsets.
 constexpr int kQ = 38;
 constexpr int kBX = 8, kBY = 4, kBN = kBX * kBY;  // brick of one 128-byte line
-__host__ __device__ inline int pad_x(int nx) { return (nx + kBX - 1) / kBX * kBX; }
-__host__ __device__ inline int pad_y(int ny) { return (ny + kBY - 1) / kBY * kBY; }
+#ifndef SC_BRICK_OX
+#define SC_BRICK_OX 0
+#endif
+#ifndef SC_BRICK_OY
+#define SC_BRICK_OY 0
+#endif
+constexpr int kOX = SC_BRICK_OX, kOY = SC_BRICK_OY;
+__host__ __device__ inline int pad_x(int nx) { return (nx + kOX + kBX - 1) / kBX * kBX; }
+__host__ __device__ inline int pad_y(int ny) { return (ny + kOY + kBY - 1) / kBY * kBY; }
 __host__ __device__ inline size_t pop_plane(int nx, int ny) {
   return (size_t)kQ * pad_x(nx) * pad_y(ny);
 }
@@ -42,11 +49,11 @@ __host__ __device__ inline size_t pop_elems(int nx, int ny, int nz) {
 // offset of population 0 of node (x, y) within its plane (0 <= x < nx,
 // 0 <= y < ny); population q is 32 q further
 __host__ __device__ inline uint32_t brick_x(int x) {
-  return (uint32_t)(x / kBX) * (uint32_t)(kQ * kBN) + (uint32_t)(x % kBX);
+  return (uint32_t)((x + kOX) / kBX) * (uint32_t)(kQ * kBN) + (uint32_t)((x + kOX) % kBX);
 }
 __host__ __device__ inline uint32_t brick_y(int y, int nx) {
-  return (uint32_t)(y / kBY) * (uint32_t)(pad_x(nx) / kBX) * (uint32_t)(kQ * kBN) +
-         (uint32_t)(y % kBY) * (uint32_t)kBX;
+  return (uint32_t)((y + kOY) / kBY) * (uint32_t)(pad_x(nx) / kBX) * (uint32_t)(kQ * kBN) +
+         (uint32_t)((y + kOY) % kBY) * (uint32_t)kBX;
 }
 // largest padded nx * ny whose three-plane pull offsets fit 32 bits of bytes
 constexpr long long kMaxPlaneNodes = (1LL << 32) / (3LL * kQ * 4) - 1;

@@ -706,7 +706,9 @@ hipError_t launch_step(const Throat *th, const TileRef *tiles, int ntiles, int t
 
 void brick_map(const uint8_t *types, int nx, int ny, int nz, std::vector<uint8_t> &live,
                size_t &nonsolid) {
-  const int nbx = pad_x(nx) / kBX, nby = pad_y(ny) / kBY;
+  // 8 x 4 patches of the tile grid (tiles start at multiples of their
+  // sides, which are multiples of 8 and 4), whatever the storage bricks' offset
+  const int nbx = (nx + kBX - 1) / kBX, nby = (ny + kBY - 1) / kBY;
   live.assign((size_t)nbx * nby * nz, 0);
   nonsolid = 0;
   for (int z = 0; z < nz; ++z)
@@ -727,8 +729,8 @@ void list_tiles(const uint8_t *live, size_t nonsolid, int nx, int ny, int nz, in
     for (size_t c = 0; c * kListNodes < nonsolid; ++c) out.push_back(TileRef{throat, (int)c});
     return;
   }
-  const int nbx = pad_x(nx) / kBX, nby = pad_y(ny) / kBY;
-  const int bpx = tx / kBX, bpy = ty / kBY;  // bricks per tile side
+  const int nbx = (nx + kBX - 1) / kBX, nby = (ny + kBY - 1) / kBY;
+  const int bpx = tx / kBX, bpy = ty / kBY;  // patches per tile side
   const int ntx = (nx + tx - 1) / tx, nty = (ny + ty - 1) / ty, ntz = (nz + lz - 1) / lz;
   // liveness of each (x-tile, y-tile) cell of every plane, then of every z-segment
   std::vector<uint8_t> cell((size_t)ntx * nty * nz, 0);
@@ -1147,6 +1149,16 @@ __device__ __forceinline__ void ramp_trial(Throat &T, RampDev &R) {
   R.steps_pt = 0;
 }
 
+// a subdomain whose state became non-finite: it stops, and the ramp points
+// from `from` on are marked non-finite (none of them gets a result)
+__device__ __forceinline__ void ramp_fail(Throat &T, RampDev &R, int *status, int from,
+                                          int n_pc) {
+  R.failed = 1;
+  R.phase = kPhaseDone;
+  T.active = 0;
+  for (int j = from; j < n_pc; ++j) status[j] = 2;  // LBM_PT_NONFINITE
+}
+
 __global__ __launch_bounds__(256) void k_ramp_advance(Throat *th, RampDev *rd, const double *pc,
                                                       RampCfg cfg, const double *sums,
                                                       const double *probe, double *S_out,
@@ -1180,9 +1192,7 @@ __global__ __launch_bounds__(256) void k_ramp_advance(Throat *th, RampDev *rd, c
       status_out[(size_t)t * cfg.n_pc + i] = st;
       R.warn |= st == 1;
       if (nonfin) {
-        R.failed = 1;
-        R.phase = kPhaseDone;
-        T.active = 0;
+        ramp_fail(T, R, status_out + (size_t)t * cfg.n_pc, i + 1, cfg.n_pc);
       } else if (!inv) {
         R.req |= kSaveStable;
         R.S_stable = S;
@@ -1207,9 +1217,9 @@ __global__ __launch_bounds__(256) void k_ramp_advance(Throat *th, RampDev *rd, c
     } else {  // bisection run finished
       R.n_bisect += 1;
       if (nonfin) {
-        R.failed = 1;
-        R.phase = kPhaseDone;
-        T.active = 0;
+        // the ramp point being bisected keeps its status; the points after
+        // it are never reached
+        ramp_fail(T, R, status_out + (size_t)t * cfg.n_pc, R.point + 1, cfg.n_pc);
       } else {
         if (inv) {
           R.hi = R.mid;

@@ -1036,9 +1036,10 @@ int lbm_surrogate_pce(lbm_surrogate_t s, int n, const lbm_params *p, const doubl
     lbm_ms = bi.wall_ms;
     for (int i = 0; i < nf; ++i) {
       const int t = fb[i];
-      used_fallback[t] = 1;
-      pce[t] = res[i].pce;
-      pce_std[t] = 0.0;
+      // 2: the LBM answer failed (non-finite state), so there is none
+      used_fallback[t] = res[i].failed ? 2 : 1;
+      pce[t] = res[i].failed ? NAN : res[i].pce;
+      pce_std[t] = res[i].failed ? NAN : 0.0;
       for (int j = 0; j < LBM_SG_NCURVE; ++j) curve[(size_t)t * LBM_SG_NCURVE + j] = S[(size_t)i * n_pc + j];
     }
   }

@@ -13,11 +13,13 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsc_lbm.so")
 
-LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ENONFINITE, LBM_ESTATE, LBM_EIO = \
+    0, -1, -2, -3, -4, -5, -6
 LBM_WNOTCONV = 1
 LBM_BC_PERIODIC, LBM_BC_WALLS, LBM_BC_RESERVOIR = 0, 1, 2
 LBM_NODE_FLUID, LBM_NODE_SOLID, LBM_NODE_RES_IN, LBM_NODE_RES_OUT = 0, 1, 2, 3
-LBM_PT_CONVERGED, LBM_PT_NOT_CONVERGED, LBM_PT_NONFINITE = 0, 1, 2
+LBM_PT_CONVERGED, LBM_PT_NOT_CONVERGED, LBM_PT_NONFINITE, LBM_PT_NOT_RUN = 0, 1, 2, 3
+LBM_WPARTIAL = 2
 LBM_SCHED_NODE_LIST = -1
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -52,7 +54,7 @@ class lbm_drain_result(ctypes.Structure):
     _fields_ = [("pce", ctypes.c_double), ("pce_lo", ctypes.c_double),
                 ("pce_hi", ctypes.c_double), ("invaded_at", ctypes.c_int),
                 ("n_bisect", ctypes.c_int), ("total_steps", ctypes.c_longlong),
-                ("S", _dp), ("steps", _llp), ("status", _ip)]
+                ("S", _dp), ("steps", _llp), ("status", _ip), ("failed", ctypes.c_int)]
 
 
 class lbm_batch_info(ctypes.Structure):
@@ -83,6 +85,13 @@ SIGNATURES = {
     "lbm_drain_batch": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(lbm_params), _dp, ctypes.c_int,
                                        ctypes.POINTER(lbm_conv), ctypes.POINTER(lbm_drain_result),
                                        ctypes.POINTER(lbm_batch_info)]),
+    "lbm_drain_begin": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_int,
+                                       ctypes.POINTER(lbm_conv)]),
+    "lbm_drain_advance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_longlong, _ip]),
+    "lbm_drain_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
+                                     ctypes.POINTER(lbm_drain_result), _ip]),
+    "lbm_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "lbm_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "lbm_time_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_longlong, _dp]),
     "lbm_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "lbm_get_schedule": (ctypes.c_int, [ctypes.c_void_p, _ip, _ip, _ip]),
@@ -90,6 +99,7 @@ SIGNATURES = {
     "lbm_bw_probe": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, _dp]),
     "lbm_step_timer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _llp]),
     "lbm_last_error": (ctypes.c_char_p, []),
+    "lbm_set_memory_budget": (ctypes.c_int, [ctypes.c_size_t]),
 }
 
 _lib = None
@@ -244,6 +254,47 @@ class Throat:
                     pce_hi=r.pce_hi, invaded_at=r.invaded_at, n_bisect=r.n_bisect,
                     total_steps=r.total_steps, warning=rc)
 
+    def drain_begin(self, pc, tol=1e-6, check_every=100, max_steps=100000, bisect_rel=0.005):
+        """Start the resumable drainage ramp (lbm_drain_begin)."""
+        pc = np.ascontiguousarray(pc, dtype=np.float64)
+        self._n_pc = pc.size
+        c = lbm_conv(float(tol), int(check_every), int(max_steps), float(bisect_rel))
+        _check(lib().lbm_drain_begin(self.h, _dptr(pc), pc.size, ctypes.byref(c)),
+               "lbm_drain_begin")
+
+    def drain_advance(self, max_steps):
+        """Run the ramp for at most max_steps lattice steps; True once it has ended."""
+        d = ctypes.c_int(0)
+        _check(lib().lbm_drain_advance(self.h, int(max_steps), ctypes.byref(d)),
+               "lbm_drain_advance")
+        return bool(d.value)
+
+    def drain_get(self, n_pc=None):
+        """Results of the resumable ramp so far (dict as drain(), plus done)."""
+        n = int(n_pc if n_pc is not None else self._n_pc)
+        S = np.zeros(n)
+        steps = np.zeros(n, dtype=np.int64)
+        status = np.zeros(n, dtype=np.int32)
+        r = lbm_drain_result()
+        r.S = _dptr(S)
+        r.steps = steps.ctypes.data_as(_llp)
+        r.status = status.ctypes.data_as(_ip)
+        d = ctypes.c_int(0)
+        rc = _check(lib().lbm_drain_get(self.h, n, ctypes.byref(r), ctypes.byref(d)),
+                    "lbm_drain_get")
+        return dict(S=S, steps=steps, status=status, pce=r.pce, pce_lo=r.pce_lo,
+                    pce_hi=r.pce_hi, invaded_at=r.invaded_at, n_bisect=r.n_bisect,
+                    total_steps=r.total_steps, failed=bool(r.failed), warning=rc,
+                    done=bool(d.value))
+
+    def save(self, path):
+        _check(lib().lbm_save(self.h, os.fsencode(path)), "lbm_save")
+
+    def load(self, path, n_pc=None):
+        _check(lib().lbm_load(self.h, os.fsencode(path)), "lbm_load")
+        if n_pc is not None:
+            self._n_pc = int(n_pc)
+
     def time_steps(self, n):
         ms = ctypes.c_double(0.0)
         _check(lib().lbm_time_steps(self.h, int(n), ctypes.byref(ms)), "lbm_time_steps")
@@ -301,12 +352,18 @@ def drain_batch(probs, pcs, tol=1e-6, check_every=100, max_steps=100000, bisect_
                                       ctypes.byref(info)), "lbm_drain_batch")
     out = [dict(S=S[i], steps=steps[i], status=status[i], pce=R[i].pce, pce_lo=R[i].pce_lo,
                 pce_hi=R[i].pce_hi, invaded_at=R[i].invaded_at, n_bisect=R[i].n_bisect,
-                total_steps=R[i].total_steps) for i in range(n)]
+                total_steps=R[i].total_steps, failed=bool(R[i].failed)) for i in range(n)]
     inf = dict(tx=info.tx, ty=info.ty, lz=info.lz, n_tiles=info.n_tiles, replays=info.replays,
                lattice_steps=info.lattice_steps, node_updates=info.node_updates,
                fluid_updates=info.fluid_updates, wall_ms=info.wall_ms, warning=rc)
     del keep
     return out, inf
+
+
+def set_memory_budget(nbytes):
+    """Refuse allocating calls that would need more than nbytes of device
+    memory (0: no budget)."""
+    _check(lib().lbm_set_memory_budget(int(nbytes)), "lbm_set_memory_budget")
 
 
 def bw_probe(nbytes=4 << 30, reps=20):

@@ -94,3 +94,98 @@ def test_invalid_arguments_rejected_without_gpu_work():
     assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
     L.lbm_throat_free(None)
     del keep
+
+
+def _batch_args(probs, pcs, conv=(1e-6, 100, 1000, 0.005)):
+    import numpy as np
+    n = len(probs)
+    P = (lbm.lbm_params * n)()
+    keep = []
+    for i, pr in enumerate(probs):
+        P[i], k = lbm.make_params(pr)
+        keep.append(k)
+    pcs = np.ascontiguousarray(pcs, dtype=np.float64)
+    n_pc = pcs.shape[1]
+    S = np.full((n, n_pc), -7.0)
+    steps = np.full((n, n_pc), -7, dtype=np.int64)
+    status = np.full((n, n_pc), -7, dtype=np.int32)
+    R = (lbm.lbm_drain_result * n)()
+    for i in range(n):
+        R[i].pce = R[i].pce_lo = R[i].pce_hi = -7.0
+        R[i].S = S[i].ctypes.data_as(lbm._dp)
+        R[i].steps = steps[i].ctypes.data_as(lbm._llp)
+        R[i].status = status[i].ctypes.data_as(lbm._ip)
+    c = lbm.lbm_conv(*conv)
+    return P, pcs, c, R, (S, steps, status), keep
+
+
+def test_drain_batch_arguments_refused_with_outputs_untouched():
+    """lbm_drain_batch validates everything before any device call: a
+    non-increasing or non-positive ramp, an odd check interval and a missing
+    probe are refused with LBM_EINVAL, and no output is written."""
+    import numpy as np
+    import synth
+    L = lbm.lib()
+    probs = [synth.small_throat_problem(seed=3), synth.small_throat_problem(seed=4)]
+    good = np.array([[0.002, 0.01], [0.002, 0.01]])
+    cases = [
+        (good * np.array([[1.0, -1.0], [1.0, 1.0]]), (1e-6, 100, 1000, 0.005), b"increasing"),
+        (good * np.array([[0.0, 1.0], [1.0, 1.0]]), (1e-6, 100, 1000, 0.005), b"positive"),
+        (good[:, ::-1].copy(), (1e-6, 100, 1000, 0.005), b"increasing"),
+        (good, (1e-6, 99, 1000, 0.005), b"check_every"),
+        (good, (0.0, 100, 1000, 0.005), b"tol"),
+        (good, (1e-6, 100, 10, 0.005), b"max_steps"),
+    ]
+    for pcs, conv, msg in cases:
+        P, pcs_a, c, R, outs, keep = _batch_args(probs, pcs, conv)
+        rc = L.lbm_drain_batch(2, P, lbm._dptr(pcs_a), pcs_a.shape[1], ctypes.byref(c), R, None)
+        assert rc == lbm.LBM_EINVAL, (pcs, conv)
+        assert msg in L.lbm_last_error(), L.lbm_last_error()
+        for a in outs:
+            assert np.all(a == -7)
+        assert all(R[i].pce == -7.0 and R[i].pce_lo == -7.0 for i in range(2))
+    # a subdomain without a probe node cannot be classified
+    probs[1].probe = None
+    P, pcs_a, c, R, outs, keep = _batch_args(probs, good)
+    assert L.lbm_drain_batch(2, P, lbm._dptr(pcs_a), 2, ctypes.byref(c), R, None) == lbm.LBM_EINVAL
+    assert b"probe" in L.lbm_last_error()
+
+
+def test_memory_budget_refuses_before_any_allocation():
+    """With a device-memory budget set, a subdomain or a batch that needs more
+    is refused with LBM_ENOMEM before any device call (this host has no GPU:
+    any device call would fail with LBM_EHIP instead), and the handle stays
+    unset; budget 0 lifts the limit again."""
+    import numpy as np
+    import synth
+    L = lbm.lib()
+    p = synth.c1_problem()
+    P, keep = lbm.make_params(p)
+    h = ctypes.c_void_p(12345)
+    try:
+        assert L.lbm_set_memory_budget(1 << 20) == lbm.LBM_OK   # 1 MiB: below a 40^3 box
+        assert L.lbm_throat_init(ctypes.byref(P), ctypes.byref(h)) == lbm.LBM_ENOMEM
+        assert b"budget" in L.lbm_last_error()
+        assert h.value == 12345
+        probs = [synth.small_throat_problem(seed=3), synth.small_throat_problem(seed=4)]
+        Pb, pcs_a, c, R, outs, keepb = _batch_args(probs, np.array([[0.002, 0.01]] * 2))
+        rc = L.lbm_drain_batch(2, Pb, lbm._dptr(pcs_a), 2, ctypes.byref(c), R, None)
+        assert rc == lbm.LBM_ENOMEM
+        assert b"budget" in L.lbm_last_error()
+        for a in outs:
+            assert np.all(a == -7)
+    finally:
+        L.lbm_set_memory_budget(0)
+    del keep
+
+
+def test_checkpoint_and_resumable_ramp_refuse_bad_arguments():
+    """lbm_save / lbm_load / lbm_drain_advance / lbm_drain_get refuse a NULL
+    handle or path before any device call."""
+    L = lbm.lib()
+    assert L.lbm_save(None, b"/tmp/x.lbm") == lbm.LBM_EINVAL
+    assert L.lbm_load(None, b"/tmp/x.lbm") == lbm.LBM_EINVAL
+    assert L.lbm_drain_advance(None, 100, None) == lbm.LBM_EINVAL
+    r = lbm.lbm_drain_result()
+    assert L.lbm_drain_get(None, 1, ctypes.byref(r), None) == lbm.LBM_EINVAL
+    assert L.lbm_drain_begin(None, None, 1, None) == lbm.LBM_EINVAL
