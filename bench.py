@@ -1,15 +1,22 @@
-"""Benchmark of the Shan-Chen throat drainage hot path on one MI355X.
+"""Benchmark of the Shan-Chen drainage hot path on one MI355X.
 
-One "step" is one full pass of the hot path over the 96^3 single-throat
-workload: voxelize the four spheres and the prism closure, set the initial
-state, then run the drainage ramp of 20 capillary pressures, each to steady
-state (|dS_w| < 1e-6 over 100 steps, capped), with bisection of the entry
-pressure.  Inputs are seeded and synthetic; the HIP library does all the work.
+Headline workload: the fully resolved 512^3 packed sample (a seeded dense
+packing of 1000 polydisperse spheres scaled to fill the box, walls on the
+sides, non-wetting bath at z = 0, wetting bath at z = 511), drained
+quasi-statically over a 12-point capillary-pressure ramp.  Geometry,
+initial state and launch shape are set up before the timed region (inputs
+resident in HBM); one timed "step" is one pass of the hot path: 400 lattice
+steps of the fused update (moments, cohesion and adhesion forces, velocity
+shift, BGK collision, pull streaming with bounce-back, bath re-imposition)
+with the FP64 saturation check every 100 steps and the ramp's decisions
+(steady state, invasion probe, next pressure or bisection, state copies), as
+lbm_drain_advance runs them.  value = fluid-node MLUPS over the timed steps.
 
-Prints one JSON line: lattice MLUPS over the whole job, the roofline of the
-fused step kernel (HIP-event timed launches inside the ramp), the FP64 CPU
-oracle timed on this host beside it, and an HBM-bound 512^3 measurement of the
-same kernel.
+Prints one JSON line with the roofline of the fused step kernel (HIP-event
+timed launches inside the ramp), the FP64 CPU oracle timed on this host on a
+crop of the same sample, and further legs: the batched drainage of 512 pore
+throats in one lbm_drain_batch call, the 96^3 single-throat drainage and the
+512^3 periodic box.  Progress goes to stderr.
 """
 import argparse
 import glob
@@ -32,15 +39,21 @@ from paper_1906_04722_amd import surrogate  # noqa: E402
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, vendor figure
 BYTES_PER_FLUID_NODE = 304   # 2 components x 19 FP32 populations, read + write
 GAMMA = synth.GAMMA_LAPLACE  # interfacial tension of the model (Laplace fit)
+# headline: the 512^3 packed sample, 12-point ramp; a timed step advances the
+# drainage by STEP_LATTICE lattice steps (checks every 100)
+SAMPLE_N, SAMPLE_SPHERES, SAMPLE_NPC = 512, 1000, 12
+SAMPLE_CONV = dict(tol=1e-6, check_every=100, max_steps=2000, bisect_rel=0.01)
+STEP_LATTICE = 400
+# single 96^3 throat: 20-point ramp to steady state, bisection to 0.5 %
 N_PC = 20
 CONV = dict(tol=1e-6, check_every=100, max_steps=20000, bisect_rel=0.005)
-# batched drainage sample: throats cut from one seeded dense packing (radii
+# batched drainage: 512 throats cut from one seeded dense packing (radii
 # lognormal, mean 1, log-sd 0.2, porosity 0.38), 32 lu per unit radius, box
-# sides 48-128, 16-point ramp, entry pressure bracketed to 1 %
-BATCH_THROATS = 24
-BATCH_SINGLES = 4
+# sides 48-128, 16-point ramp, entry pressure bracketed to 1 %, all in one
+# lbm_drain_batch call
+BATCH_THROATS = 512
 BATCH_N_PC = 16
-BATCH_CONV = dict(tol=1e-6, check_every=100, max_steps=4000, bisect_rel=0.01)
+BATCH_CONV = dict(tol=1e-6, check_every=100, max_steps=600, bisect_rel=0.01)
 # learned surrogate: trained on throats of one packing drained by the batched
 # LBM, evaluated on throats of another packing against the plain LBM
 SG_TEST, SG_INFER = 256, 100000
@@ -49,10 +62,6 @@ SG_RES, SG_SIDES = 12.0, (24, 64)
 SG_CONV = dict(tol=1e-6, check_every=100, max_steps=1500, bisect_rel=0.01)
 SG_FIT = dict(epochs=200, batch=64, lr=1e-3, seed=2)
 SG_THRESHOLD = 0.02
-# fully resolved sample: a dense packing filling a 512^3 box, 12-point ramp
-# with a short per-point cap (throughput measurement of the same step)
-SAMPLE_N, SAMPLE_SPHERES = 512, 1000
-SAMPLE_CONV = dict(tol=1e-6, check_every=50, max_steps=100, bisect_rel=0.01)
 # hybrid assembly: pore network of a 40-sphere packing (the paper's sample
 # size), each throat's entry pressure from the batched LBM, then the
 # network drainage with trapping
@@ -60,7 +69,7 @@ HYB_SPHERES = 40
 HYB_CONV = dict(tol=1e-6, check_every=100, max_steps=1500, bisect_rel=0.01)
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix cores, vendor figure
 KERNEL_SRC = os.path.join(ROOT, "paper_1906_04722_amd", "csrc", "sc_kernels.hip")
-TRAFFIC_GLOB = os.path.join(ROOT, "profiles", "k_step_c2_96_*traffic.txt")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(msg):
@@ -73,11 +82,12 @@ def kernel_sha():
     return sha(KERNEL_SRC)
 
 
-def read_traffic(schedule):
-    """HBM bytes per step from a committed counter summary of the 96^3 step,
-    taken on the current kernel source with the same launch shape; else None."""
+def read_traffic(prefix, schedule):
+    """HBM bytes per step from a committed counter summary (profiles/
+    <prefix>*traffic.txt) taken on the current kernel source with the same
+    launch shape; else None."""
     want = ",".join(str(int(v)) for v in schedule)
-    for path in sorted(glob.glob(TRAFFIC_GLOB)):
+    for path in sorted(glob.glob(os.path.join(PROFILES, prefix + "*traffic.txt"))):
         kv = {}
         for line in open(path):
             if ":" in line and not line.startswith("#"):
@@ -123,58 +133,115 @@ def one_drain(p, pcs, schedule=None):
     return out, ms, launches, n_fluid
 
 
-def cpu_baseline(p, budget_s=12.0):
-    """The FP64 oracle (test infrastructure) on this host's cores: a bounded
-    sample of the same workload (the same throat at a fixed inlet density,
-    whole steps until the time budget is used)."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _omp_threads(n=None):
+    """Set (n) or read the OpenMP thread count of this process (the oracle's
+    loops run on the process's one OpenMP runtime)."""
+    import ctypes
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+    if n is not None:
+        gomp.omp_set_num_threads(int(n))
+    return int(gomp.omp_get_max_threads())
+
+
+def _sample_crop(p, n=128):
+    """A crop of the packed sample: the n^3 window at the box centre with the
+    spheres that reach into it, walls on all sides, wetting fluid."""
+    S = np.asarray(p.spheres, dtype=np.float64).copy()
+    o = np.array([(p.nx - n) // 2, (p.ny - n) // 2, (p.nz - n) // 2], dtype=np.float64)
+    S[:, :3] -= o
+    keep = np.all((S[:, :3] + S[:, 3:4] > -2) & (S[:, :3] - S[:, 3:4] < n + 1), axis=1)
+    rho0 = synth.layered_density(n, n, n, -1, p.rho_major, p.rho_minor)
+    return synth.Problem(nx=n, ny=n, nz=n, bc=(synth.BC_WALLS,) * 3, spheres=S[keep],
+                         rho_init=rho0, probe=None)
+
+
+def cpu_baseline(p, budget_s=10.0):
+    """The FP64 oracle (test infrastructure, as it stands) on this host: a
+    128^3 crop of the packed sample, timed for about budget_s of whole steps
+    on all cores and again on one core.  Fluid-node MLUPS (the crop's fluid
+    nodes x steps / s), the unit of the headline value."""
     import oracle
-    o = oracle.Oracle(p)
-    o.step(2)
-    n = 0
+    c = _sample_crop(p)
+    o = oracle.Oracle(c)
+    n_fluid = int((o.types() == oracle.FLUID).sum())
+    all_threads = _omp_threads()
+    runs = {}
+    for label, threads in (("all", all_threads), ("one", 1)):
+        if threads is not None:
+            _omp_threads(threads)
+        o.step(1)
+        n = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            o.step(2)
+            n += 2
+        dt = time.perf_counter() - t0
+        runs[label] = dict(threads=_omp_threads() if threads is not None else None,
+                           steps=n, seconds=round(dt, 2),
+                           fluid_MLUPS=round(n_fluid * n / dt / 1e6, 3),
+                           MLUPS=round(c.n_nodes * n / dt / 1e6, 3))
+    if all_threads is not None:
+        _omp_threads(all_threads)
+    return {"value": runs["all"]["fluid_MLUPS"], "unit": "fluid MLUPS",
+            "cores": runs["all"]["threads"], "kind": "oracle",
+            "sample": f"128^3 crop of the 512^3 packed sample ({n_fluid} fluid nodes), FP64, "
+                      f"{runs['all']['steps']} steps on all cores and {runs['one']['steps']} on "
+                      "one core, about 10 s each",
+            "one_core_fluid_MLUPS": runs["one"]["fluid_MLUPS"], "runs": runs,
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def batch_leg(n_throats=BATCH_THROATS):
+    """Batched drainage of n_throats packing throats in one lbm_drain_batch
+    call: throats per second (all, and those with an entry pressure
+    bracketed to 1 %) over the call's wall time (subdomain setup, autotuning
+    and the whole graph-replayed ramp; the packing and throat geometry are
+    generated on the host before it)."""
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        o.step(20)
-        n += 20
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(p.n_nodes * n / dt / 1e6, 2), "unit": "MLUPS", "cores": cores,
-            "kind": "oracle",
-            "sample": f"96^3 throat, {n} FP64 steps at a fixed inlet density ({dt:.1f} s)"}
-
-
-def batch_leg(n_throats=BATCH_THROATS, n_single=BATCH_SINGLES):
-    """Batched drainage of packing throats in one lbm_drain_batch call, and the
-    first few of the same throats drained one at a time (lbm_drain_throat,
-    autotuned) on the same GPU for comparison."""
     probs, rins, summ = synth.packing_throats(n_throats=n_throats, seed=3)
     pcs = np.array([synth.pc_ramp(GAMMA, ri, BATCH_N_PC) for ri in rins])
+    log(f"batch: {len(probs)} throats generated on the host in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
     out, info = lbm.drain_batch(probs, pcs, **BATCH_CONV)
     dt = time.perf_counter() - t0
-    log(f"batch: {n_throats} throats drained in {dt:.1f} s")
-    ok = sum(1 for o in out if o["invaded_at"] >= 0
+    log(f"batch: {len(probs)} throats drained in {dt:.1f} s")
+    ok = sum(1 for o in out if o["invaded_at"] >= 0 and not o["failed"]
              and (o["pce_hi"] - o["pce_lo"]) <= BATCH_CONV["bisect_rel"] * o["pce_hi"])
+    st = np.concatenate([o["status"] for o in out])
     fl = info["fluid_updates"] / (info["wall_ms"] * 1e-3)
-    t1 = time.perf_counter()
-    single_steps = 0
-    for p, pc in zip(probs[:n_single], pcs[:n_single]):
-        g = lbm.Throat(p)
-        g.autotune(20)
-        single_steps += g.drain(pc, **BATCH_CONV)["total_steps"]
-        g.close()
-    dt1 = time.perf_counter() - t1
     gbs = fl * BYTES_PER_FLUID_NODE / 1e9
-    return {"workload": f"{n_throats} throats cut from a seeded dense packing ({summ['n_spheres']} "
-                        "spheres, radii lognormal mean 1 sigma 0.2, porosity 0.38), 32 lu per unit "
-                        f"radius, sides 48-128, {BATCH_N_PC}-point ramp, cap "
-                        f"{BATCH_CONV['max_steps']} steps per point, p_c^e bracket 1 %",
-            "throats": n_throats, "box_nodes": int(sum(p.n_nodes for p in probs)),
-            "throats_per_s": round(n_throats / dt, 3), "wall_s": round(dt, 2),
-            "pce_bracketed_1pct": ok, "fluid_MLUPS": round(fl / 1e6, 1),
-            "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+    return {"workload": f"{len(probs)} throats cut from a seeded dense packing "
+                        f"({summ['n_spheres']} spheres, radii lognormal mean 1 sigma 0.2, porosity "
+                        f"{summ['porosity']:.2f}), 32 lu per unit radius, box sides 48-128, "
+                        f"{BATCH_N_PC}-point ramp, |dS_w| < {BATCH_CONV['tol']:g} per 100 steps "
+                        f"capped at {BATCH_CONV['max_steps']} steps per point, p_c^e bracket 1 %, "
+                        "one lbm_drain_batch call",
+            "throats": len(probs), "box_nodes": int(sum(p.n_nodes for p in probs)),
+            "wall_s": round(dt, 2), "device_ms": round(info["wall_ms"], 1),
+            "throats_per_s": round(len(probs) / dt, 3),
+            "pce_bracketed_1pct": ok, "bracketed_throats_per_s": round(ok / dt, 3),
+            "failed": int(sum(o["failed"] for o in out)),
+            "points_converged": int((st == lbm.LBM_PT_CONVERGED).sum()),
+            "points_capped": int((st == lbm.LBM_PT_NOT_CONVERGED).sum()),
+            "fluid_MLUPS": round(fl / 1e6, 1), "achieved_GBps": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "frac_note": "fluid-node updates x 304 B over the device time of the whole drain "
+                         "(steps, reductions, decisions, checkpoint copies)",
             "schedule": [info["tx"], info["ty"], info["lz"]], "graph_replays": info["replays"],
-            "single_throat_drains": {"throats": n_single, "throats_per_s": round(n_single / dt1, 3),
-                                     "lattice_steps": int(single_steps)}}
+            "lattice_steps": info["lattice_steps"]}
 
 
 def surrogate_leg():
@@ -295,34 +362,24 @@ def surrogate_leg():
             "inference_rows_per_s": round(SG_INFER / t_inf, 1)}
 
 
-def sample_512():
-    """The fused step on the fully resolved 512^3 packed sample: walls, baths,
-    a 12-point drainage ramp with a short cap per point (throughput only)."""
+def sample_setup():
+    """The 512^3 packed sample on the GPU, its launch shape autotuned, and its
+    drainage ramp begun (all before the timed region)."""
     p, summ = synth.packed_sample(SAMPLE_N, SAMPLE_SPHERES, seed=4)
     g = lbm.Throat(p)
     sched = g.autotune(4)
     n_fluid = int((g.types() == lbm.LBM_NODE_FLUID).sum())
     r_ins = (2.0 / np.sqrt(3.0) - 1.0) * summ["mean_radius_lu"]  # three touching spheres
-    pcs = synth.pc_ramp(GAMMA, r_ins, 12)
-    g.step_timer(1)
-    t0 = time.perf_counter()
-    out = g.drain(pcs, **SAMPLE_CONV)
-    wall = time.perf_counter() - t0
-    ms, launches = g.step_timer(-1)
-    g.close()
-    avg = ms * 1e-3 / max(launches, 1)
-    gbs = n_fluid * BYTES_PER_FLUID_NODE / avg / 1e9
-    nodes = p.nx * p.ny * p.nz
-    return {"workload": f"512^3 packed sample: {summ['spheres_in_box']} spheres in the box "
-                        f"(packing of {SAMPLE_SPHERES}, mean radius {summ['mean_radius_lu']:.1f} lu), "
-                        "walls, baths at z = 0 / 511, 12-point ramp, "
-                        f"{SAMPLE_CONV['max_steps']} steps cap per point",
-            "nodes": nodes, "fluid_nodes": n_fluid, "schedule": list(sched),
-            "lattice_steps": int(out["total_steps"]), "wall_s": round(wall, 2),
-            "ms_per_step": round(avg * 1e3, 4), "MLUPS": round(nodes / avg / 1e6, 1),
-            "fluid_MLUPS": round(n_fluid / avg / 1e6, 1), "achieved_GBps": round(gbs, 1),
-            "peak_GBps": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4),
-            "S_w": [round(float(x), 5) for x in out["S"]]}
+    pcs = synth.pc_ramp(GAMMA, r_ins, SAMPLE_NPC)
+    g.drain_begin(pcs, **SAMPLE_CONV)
+    return p, summ, g, sched, n_fluid, pcs
+
+
+def advance(g, pcs):
+    """One bench step: STEP_LATTICE lattice steps of the drainage (a ramp that
+    has ended starts over from the state it reached)."""
+    if g.drain_advance(STEP_LATTICE):
+        g.drain_begin(pcs, **SAMPLE_CONV)
 
 
 def _hybrid(x, r, L, res, state, name):
@@ -510,26 +567,62 @@ def dense_512(steps=10):
             "peak_GBps": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def c2_leg(schedule=None):
+    """The 96^3 single throat: one drainage ramp of 20 pressures with
+    bisection (lbm_drain_throat), launch shape autotuned, each ramp point's
+    convergence status reported."""
+    p, pcs = c2_workload()
+    t0 = time.perf_counter()
+    out, ms, launches, n_fluid = one_drain(p, pcs, schedule)
+    dt = time.perf_counter() - t0
+    avg = ms * 1e-3 / max(launches, 1)
+    gbs = n_fluid * BYTES_PER_FLUID_NODE / avg / 1e9
+    return {"workload": "96^3 single pore throat: 4 spheres, lognormal radii (mean 32 lu, sigma "
+                        "0.15) on a jittered tetrahedron, prism closure, 20-point drainage ramp, "
+                        f"|dS_w| < {CONV['tol']:g} per 100 steps capped at {CONV['max_steps']} steps "
+                        "per point, bisection of p_c^e to 0.5 %",
+            "fluid_nodes": n_fluid, "wall_s": round(dt, 2),
+            "lattice_steps": int(out["total_steps"]),
+            "MLUPS": round(p.n_nodes * out["total_steps"] / dt / 1e6, 1),
+            "fluid_MLUPS": round(n_fluid * out["total_steps"] / dt / 1e6, 1),
+            "schedule": list(out["schedule"]), "ms_per_step": round(avg * 1e3, 5),
+            "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": read_traffic("k_step_c2_96_", out["schedule"]),
+            "kernel": step_kernels(out["schedule"]),
+            "pce": lbm.nan_safe(out["pce"]), "pce_bracket": [out["pce_lo"], lbm.nan_safe(out["pce_hi"])],
+            "invaded_at": int(out["invaded_at"]),
+            "points_converged": int((out["status"] == lbm.LBM_PT_CONVERGED).sum()),
+            "points_capped": int((out["status"] == lbm.LBM_PT_NOT_CONVERGED).sum()),
+            "status": [int(v) for v in out["status"]],
+            "drainage_curve": {"pc": [round(float(x), 6) for x in pcs],
+                               "S_w": [round(float(x), 6) for x in out["S"]]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--no-sample", action="store_true")
-    ap.add_argument("--no-hybrid", action="store_true")
-    ap.add_argument("--no-full", action="store_true")
-    ap.add_argument("--no-three", action="store_true")
+    ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--batch-throats", type=int, default=BATCH_THROATS)
+    ap.add_argument("--surrogate", action="store_true",
+                    help="also train and evaluate the learned entry-pressure surrogate")
+    ap.add_argument("--three", action="store_true",
+                    help="also run the three-touching-sphere throat at several radii")
+    ap.add_argument("--hybrid", action="store_true",
+                    help="also run the hybrid pore-network drainage of a 40-sphere packing")
+    ap.add_argument("--full", action="store_true",
+                    help="also run that packing fully resolved with the membrane (minutes)")
+    ap.add_argument("--paper40", action="store_true",
+                    help="also run the replica of the paper's 40-sphere sample (about 2 min)")
     ap.add_argument("--sg-train", type=int, default=SG_CFG["train"],
                     help="throats drained to train the surrogate (default 512, at most ~6000)")
     ap.add_argument("--schedule", default="",
-                    help="launch shape tx,ty,lz of the 96^3 drains (e.g. --schedule=-1,0,0 for "
+                    help="launch shape tx,ty,lz of the 96^3 drain (e.g. --schedule=-1,0,0 for "
                          "the node list) instead of the autotuner's pick")
-    ap.add_argument("--paper40", action="store_true",
-                    help="also run the replica of the paper's 40-sphere sample (about 2 min)")
     ap.add_argument("--three-radii", default=",".join(f"{v:g}" for v in THREE_CFG["radii"]),
                     help="sphere radii (lattice units) of the three-sphere throat leg")
     ap.add_argument("--full-cap", type=int, default=FULL_CONV["max_steps"],
@@ -541,38 +634,40 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    p, pcs = c2_workload()
-    fixed = tuple(int(v) for v in a.schedule.split(",")) if a.schedule else None
-    for i in range(a.warmup):
-        one_drain(p, pcs, fixed)
-        log(f"warmup drain {i + 1}/{a.warmup} done")
-
+    # headline: the 512^3 packed sample; setup (voxelize, initial state,
+    # autotune, ramp begun) before the timed region
     t0 = time.perf_counter()
-    results = []
+    p, summ, g, sched, n_fluid, pcs = sample_setup()
+    log(f"512^3 sample ready in {time.perf_counter() - t0:.1f} s, schedule {sched}, "
+        f"{n_fluid} fluid nodes")
+    for i in range(a.warmup):
+        advance(g, pcs)
+        log(f"warmup step {i + 1}/{a.warmup} done")
+    g.sync()
+    g.step_timer(1)
+    t0 = time.perf_counter()
     for i in range(a.steps):
-        results.append(one_drain(p, pcs, fixed))
-        log(f"timed drain {i + 1}/{a.steps} done")
+        advance(g, pcs)
+        log(f"timed step {i + 1}/{a.steps} done")
+    g.sync()
     dt = time.perf_counter() - t0
-
-    total_steps = sum(r[0]["total_steps"] for r in results)
-    node_updates = p.n_nodes * total_steps
-    n_fluid = results[0][3]
-    mlups = node_updates / dt / 1e6
-    k_ms = sum(r[1] for r in results)
-    k_launches = sum(r[2] for r in results)
+    k_ms, k_launches = g.step_timer(-1)
+    g.step_timer(0)
+    ramp = g.drain_get()
+    g.close()
+    lattice = k_launches   # one fused-step launch per lattice step
+    fluid_mlups = n_fluid * lattice / dt / 1e6
     avg_launch_s = k_ms * 1e-3 / max(k_launches, 1)
     alg_bytes = n_fluid * BYTES_PER_FLUID_NODE
     achieved = alg_bytes / avg_launch_s / 1e9
-    out = results[-1][0]
-
     line = {
         "metric": "MLUPS + % HBM roofline (Shan-Chen FP32); throats/sec to p_c^e at \u22641% err",
-        "value": round(mlups, 1),
+        "value": round(fluid_mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(dt / a.steps * 1e3, 1),
+        "ms_per_step": round(dt / max(a.steps, 1) * 1e3, 1),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -580,36 +675,46 @@ def main():
         "storage_dtype": "f32",
         "sum_dtype": "f64",
         "data": "synthetic (seeded)",
-        "config": {"workload": "96^3 single pore throat: 4 spheres, lognormal radii (mean 32 lu, "
-                               "sigma 0.15) on a jittered tetrahedron, prism closure, 20-point "
-                               "drainage ramp to steady state + bisection of p_c^e",
-                   "nx": p.nx, "ny": p.ny, "nz": p.nz, "n_pc": N_PC,
-                   "fluid_nodes": n_fluid, "tol": CONV["tol"],
-                   "check_every": CONV["check_every"], "max_steps_per_point": CONV["max_steps"]},
-        "fluid_MLUPS": round(n_fluid * total_steps / dt / 1e6, 1),
-        "lattice_steps_per_drain": total_steps // a.steps,
-        "schedule": list(out["schedule"]),
-        "schedule_source": "fixed (--schedule)" if fixed else "autotuned",
-        "pce": lbm.nan_safe(out["pce"]),
-        "pce_bracket": [out["pce_lo"], lbm.nan_safe(out["pce_hi"])],
-        "drainage_curve": {"pc": [round(float(x), 6) for x in pcs],
-                           "S_w": [round(float(x), 6) for x in out["S"]]},
+        "config": {"workload": f"512^3 fully resolved packed sample: {summ['spheres_in_box']} "
+                               f"spheres in the box (dense packing of {SAMPLE_SPHERES}, radii "
+                               f"lognormal, mean {summ['mean_radius_lu']:.1f} lu), walls, baths at "
+                               f"z = 0 / 511, {SAMPLE_NPC}-point drainage ramp (|dS_w| < "
+                               f"{SAMPLE_CONV['tol']:g} per 100 steps, capped at "
+                               f"{SAMPLE_CONV['max_steps']} per point, bisection to 1 %); one step "
+                               f"= {STEP_LATTICE} lattice steps of the ramp",
+                   "nx": p.nx, "ny": p.ny, "nz": p.nz, "fluid_nodes": n_fluid,
+                   "lattice_steps_per_step": STEP_LATTICE},
+        "value_kind": "fluid-node MLUPS (fluid nodes x lattice steps / wall time of the timed steps)",
+        "box_MLUPS": round(p.n_nodes * lattice / dt / 1e6, 1),
+        "lattice_steps_timed": int(lattice),
+        "schedule": list(sched),
+        "ramp": {"pc": [round(float(x), 6) for x in pcs],
+                 "S_w_so_far": [round(float(x), 6) for x in ramp["S"]],
+                 "status_so_far": [int(x) for x in ramp["status"]],
+                 "steps_so_far": int(ramp["total_steps"])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": read_traffic(out["schedule"]),
-                     "kernel": step_kernels(out["schedule"]),
-                     "launches": k_launches, "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                     "alg_bytes_per_launch": alg_bytes},
+                     "traffic": read_traffic("k_step_sample_512", sched),
+                     "kernel": step_kernels(sched),
+                     "launches": int(k_launches), "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                     "alg_bytes_per_launch": alg_bytes,
+                     "alg_bytes_note": "fluid nodes x 304 B (38 FP32 populations read and written)"},
     }
+    log(f"headline: {fluid_mlups:.0f} fluid MLUPS, step kernel {avg_launch_s * 1e3:.3f} ms, "
+        f"{achieved / HBM_PEAK_GBS:.3f} of 8 TB/s")
     line["copy_probe_GBps"] = round(lbm.bw_probe(4 << 30, 10), 1)
     FULL_CONV["max_steps"] = a.full_cap
     SG_CFG["train"] = a.sg_train
     THREE_CFG["radii"] = tuple(float(v) for v in a.three_radii.split(","))
-    legs = [("batch", a.no_batch, batch_leg), ("surrogate", a.no_surrogate, surrogate_leg),
-            ("three_sphere", a.no_three, three_sphere_leg),
-            ("hybrid_40", a.no_hybrid, hybrid_leg), ("full_40", a.no_full, full_leg),
+    fixed = tuple(int(v) for v in a.schedule.split(",")) if a.schedule else None
+    legs = [("batch", a.no_batch, lambda: batch_leg(a.batch_throats)),
+            ("c2_96", a.no_c2, lambda: c2_leg(fixed)),
+            ("dense_512", a.no_dense, dense_512),
+            ("surrogate", not a.surrogate, surrogate_leg),
+            ("three_sphere", not a.three, three_sphere_leg),
+            ("hybrid_40", not (a.hybrid or a.full), hybrid_leg),
+            ("full_40", not a.full, full_leg),
             ("paper_40", not a.paper40, paper40_leg),
-            ("dense_512", a.no_dense, dense_512), ("sample_512", a.no_sample, sample_512),
             ("cpu_baseline", a.no_cpu, lambda: cpu_baseline(p))]
     for name, skip, fn in legs:
         if skip:

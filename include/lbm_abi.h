@@ -283,7 +283,10 @@ typedef struct {
  * LBM_WNOTCONV if a point hit its cap, LBM_WPARTIAL if a subdomain became
  * non-finite: its result has failed = 1, NaN entry pressures and
  * LBM_PT_NONFINITE from the failing point on; the other subdomains are
- * complete and equal their single drains.  info may be NULL. */
+ * complete and equal their single drains.  info may be NULL.
+ * With LBM_BATCH_NO_GRAPH=1 in the environment the chunks are launched
+ * kernel by kernel instead of replayed as a graph (for tracers that do not
+ * follow graph launches); the results are the same bit for bit. */
 int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, const lbm_conv *c,
                     lbm_drain_result *out, lbm_batch_info *info);
 

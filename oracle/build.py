@@ -9,7 +9,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["sc_oracle.c", "mlp_oracle.c"]
+SOURCES = ["sc_oracle.c"]
 LIB = os.path.join(HERE, "libsc_oracle.so")
 
 

@@ -30,9 +30,12 @@ the LBM runs only where an ensemble of networks disagrees.
   v = b2 v + (1 - b2) g^2, w -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 * Ensemble: mean and population standard deviation over members; a throat
   falls back to the LBM when std(p) > threshold * |mean(p)| for output 0.
-* Opening radius (the scale of output 0, which is p_c^e times it): the
-  circle in the prism's cross-section (xy) tangent from outside to the three
-  throat-sphere circles, found by a root finder from the centroid.
+* Targets: output 0 is p_c^e times the throat's MS-P entry radius (computed
+  by the HIP library from the three throat circles; a throat without one is
+  left out), outputs 1-16 the ramp's saturations.
+* Opening radius (kept as a geometric reference): the circle in the prism's
+  cross-section (xy) tangent from outside to the three throat-sphere
+  circles, found by a root finder from the centroid.
 """
 import numpy as np
 

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "lbm_abi.h"
@@ -52,6 +53,9 @@ struct Batch {
   sc::Sched sched{32, 4, 2};
 
   ~Batch() {
+    // an error return can leave replays queued: let them finish before any
+    // graph, buffer or handle they use is released
+    if (stream) (void)hipStreamSynchronize(stream);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (void *p : {(void *)th_d, (void *)tiles_d, (void *)zper_d, (void *)chunks_d, (void *)cchunks_d,
@@ -173,8 +177,9 @@ int autotune(Batch &B, int trial_steps) {
   return build_tiles(B, cand[best]);
 }
 
-int capture_chunk(Batch &B, const sc::RampCfg &cfg) {
-  BCHK(hipStreamBeginCapture(B.stream, hipStreamCaptureModeThreadLocal));
+// the kernels of one chunk: check_every fused steps, the reductions, the
+// ramp decisions and the checkpoint copies they request
+hipError_t enqueue_chunk(Batch &B, const sc::RampCfg &cfg) {
   hipError_t e = hipSuccess;
   for (int i = 0; i < cfg.every && e == hipSuccess; ++i)
     e = sc::launch_step(B.th_d, B.tiles_d, B.ntiles, B.sched.tx, B.sched.ty, i & 1, B.stream,
@@ -189,6 +194,12 @@ int capture_chunk(Batch &B, const sc::RampCfg &cfg) {
                                 B.status_d, B.n, B.nact_d, B.stream);
   if (e == hipSuccess)
     e = sc::launch_copy_requests(B.th_d, B.rd_d, B.ck_d, B.cchunks_d, B.ncchunks, 0, B.stream);
+  return e;
+}
+
+int capture_chunk(Batch &B, const sc::RampCfg &cfg) {
+  BCHK(hipStreamBeginCapture(B.stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue_chunk(B, cfg);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(B.stream, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -348,7 +359,13 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
   BCHK(sc::launch_reduce_throats(B.first_d, B.count_d, n, B.partials, B.sums, B.stream));
   BCHK(sc::launch_ramp_begin(B.th_d, B.rd_d, B.pc_d, cfg, B.sums, n, B.stream));
   BCHK(sc::launch_copy_requests(B.th_d, B.rd_d, B.ck_d, B.cchunks_d, B.ncchunks, 0, B.stream));
-  if (int r = capture_chunk(B, cfg)) return r;
+  // LBM_BATCH_NO_GRAPH=1 in the environment: the same chunk launched kernel
+  // by kernel instead of replayed as a graph (for tracers that do not
+  // follow graph launches); results are identical
+  const char *ng = std::getenv("LBM_BATCH_NO_GRAPH");
+  const bool use_graph = !(ng && ng[0] == '1');
+  if (use_graph)
+    if (int r = capture_chunk(B, cfg)) return r;
   // replay until every subdomain has finished its ramp; a bound on the
   // replays guards against a run that would never end
   const long long max_bisect = sc::kMaxBisect;
@@ -358,7 +375,12 @@ int lbm_drain_batch(int n, const lbm_params *p, const double *pc, int n_pc, cons
   long long replays = 0;
   const int poll = 4;
   for (;;) {
-    for (int i = 0; i < poll; ++i) BCHK(hipGraphLaunch(B.exec, B.stream));
+    for (int i = 0; i < poll; ++i) {
+      if (use_graph)
+        BCHK(hipGraphLaunch(B.exec, B.stream));
+      else
+        BCHK(enqueue_chunk(B, cfg));
+    }
     replays += poll;
     BCHK(hipMemcpyAsync(B.nact_h, B.nact_d, sizeof(int), hipMemcpyDeviceToHost, B.stream));
     BCHK(hipStreamSynchronize(B.stream));

@@ -3,7 +3,8 @@ writer for the counter output.
 
   python3 -m paper_1906_04722_amd.profile_run run --steps 200 [--autotune 20]
       builds the 96^3 throat (or an N^3 periodic box with --workload N, or the
-      512^3 packed sample with --workload sample512), runs
+      512^3 packed sample with --workload sample512; --workload batchN drains N
+      packing throats in one batch instead, --steps capping each ramp point), runs
       a 1 GiB copy twice (the counter calibration: 2 GiB moved per launch,
       known exactly) and `steps` fused steps, optionally after autotuning the
       launch shape as the benchmark does.
@@ -42,6 +43,24 @@ def cmd_run(a):
     import synth
     from paper_1906_04722_amd import lbm
     lbm.bw_probe(COPY_BYTES, 2)
+    if a.workload.startswith("batch"):
+        # batched drainage of N packing throats (32 lu per unit radius, sides
+        # 48-128), a 16-point ramp capped at --steps steps per point; chunks
+        # launched kernel by kernel (--no-graph) for tracers that do not
+        # follow graph launches
+        import numpy as np
+        n = int(a.workload[len("batch"):] or 64)
+        probs, rins, _ = synth.packing_throats(n_throats=n, seed=3)
+        pcs = np.array([synth.pc_ramp(synth.GAMMA_LAPLACE, r, 16) for r in rins])
+        if a.no_graph:
+            os.environ["LBM_BATCH_NO_GRAPH"] = "1"
+        out, info = lbm.drain_batch(probs, pcs, tol=1e-6, check_every=100, max_steps=a.steps,
+                                    bisect_rel=0.01)
+        print(f"profile_run: {a.workload}, cap {a.steps} per point, schedule "
+              f"{[info['tx'], info['ty'], info['lz']]}, lattice steps {info['lattice_steps']}, "
+              f"fluid updates {info['fluid_updates']}, {info['n_tiles']} tiles, graph "
+              f"{'off' if a.no_graph else 'on'}", flush=True)
+        return
     if a.workload == "c2":
         p = synth.c2_problem()
     elif a.workload == "sample512":
@@ -124,6 +143,8 @@ def main():
                    help="trial steps of the launch-shape autotuner before the run (0: default shape)")
     r.add_argument("--schedule", default="",
                    help="launch shape tx,ty,lz to run with (e.g. the one the benchmark's autotuner picks)")
+    r.add_argument("--no-graph", action="store_true",
+                   help="batch workloads: launch each chunk's kernels instead of a graph replay")
     s = sub.add_parser("summarize")
     s.add_argument("--stats", required=True)
     s.add_argument("--fetch", required=True)

@@ -101,3 +101,21 @@ def test_invaded_at_the_first_point_ends_with_a_bracket():
     (b,), _ = lbm.drain_batch([p], pc[None, :], **conv)
     assert b["n_bisect"] == 40 and b["pce_hi"] == s["pce_hi"]
     assert np.array_equal(b["S"], s["S"]) and b["total_steps"] == s["total_steps"]
+
+
+def test_batch_without_graph_equals_graph_replay(monkeypatch):
+    """LBM_BATCH_NO_GRAPH=1 launches each chunk's kernels one by one instead
+    of replaying the captured graph: the same kernels in the same order, so
+    the results are bit-identical."""
+    from paper_1906_04722_amd import lbm
+    probs, pcs = _throats()
+    probs, pcs = probs[:2], pcs[:2]
+    a, ia = lbm.drain_batch(probs, pcs, **CONV)
+    monkeypatch.setenv("LBM_BATCH_NO_GRAPH", "1")
+    b, ib = lbm.drain_batch(probs, pcs, **CONV)
+    assert ia["replays"] == ib["replays"]
+    for x, y in zip(a, b):
+        for k in ("S", "steps", "status"):
+            assert np.array_equal(x[k], y[k])
+        assert np.array_equal([x["pce"], x["pce_lo"], x["pce_hi"]],
+                              [y["pce"], y["pce_lo"], y["pce_hi"]], equal_nan=True)

@@ -40,13 +40,14 @@ def test_traffic_is_taken_by_hash_and_schedule(tmp_path, monkeypatch):
     import bench
     src = _write(tmp_path, "k.hip", CODE)
     monkeypatch.setattr(bench, "KERNEL_SRC", src)
-    monkeypatch.setattr(bench, "TRAFFIC_GLOB", str(tmp_path / "k_step_c2_96_*traffic.txt"))
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
     sha = kernel_sha(src)
     (tmp_path / "k_step_c2_96_list_traffic.txt").write_text(
         f"# node list\nkernel_sha: {sha}\nschedule: -1,0,0\ntraffic_bytes_per_launch: 123\n")
     (tmp_path / "k_step_c2_96_old_traffic.txt").write_text(
         "# another source\nkernel_sha: 0000000000000000\nschedule: 16,8,1\n"
         "traffic_bytes_per_launch: 456\n")
-    assert bench.read_traffic((-1, 0, 0)) == 123.0
-    assert bench.read_traffic((16, 8, 1)) is None   # taken on other code
-    assert bench.read_traffic((32, 4, 1)) is None   # no summary for this shape
+    assert bench.read_traffic("k_step_c2_96_", (-1, 0, 0)) == 123.0
+    assert bench.read_traffic("k_step_c2_96_", (16, 8, 1)) is None   # taken on other code
+    assert bench.read_traffic("k_step_c2_96_", (32, 4, 1)) is None   # no summary for this shape
+    assert bench.read_traffic("k_step_sample_512", (-1, 0, 0)) is None   # another workload
