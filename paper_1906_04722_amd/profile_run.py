@@ -8,6 +8,9 @@ writer for the counter output.
       a 1 GiB copy twice (the counter calibration: 2 GiB moved per launch,
       known exactly) and `steps` fused steps, optionally after autotuning the
       launch shape as the benchmark does.
+  python3 -m paper_1906_04722_amd.profile_run trace --trace T.csv --kernel K --last N
+      --out profiles/NAME.txt: per-kernel statistics of a kernel trace and the
+      average of kernel K's last N dispatches (a benchmark's timed region).
   python3 -m paper_1906_04722_amd.profile_run summarize --stats S.csv
       --fetch F.csv --write W.csv --out profiles/NAME.txt --command "..."
       writes the per-step averages of the step kernels (the fused k_step, or
@@ -107,7 +110,7 @@ def cmd_summarize(a):
     w_scale = COPY_BYTES / (sum(cw) / len(cw) * 1024.0)
     fb = wb = 0.0
     counted = []
-    for key in a.kernels.split(","):
+    for key in [k for k in a.kernels.split(";" if ";" in a.kernels else ",") if k]:
         sf = find(fetch, key)
         sw = find(write, key)
         fb += sum(sf) / len(sf) * 1024.0 * f_scale
@@ -133,6 +136,37 @@ def cmd_summarize(a):
     print("\n".join(lines))
 
 
+def cmd_trace(a):
+    """Summary of a kernel trace: per-kernel statistics, and for one kernel
+    the average of its last `last` dispatches (the timed region of a run
+    whose earlier dispatches include autotuner trials)."""
+    rows = list(csv.DictReader(open(a.trace)))
+    per = {}
+    for r in rows:
+        d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        per.setdefault(r["Kernel_Name"], []).append((int(r["Start_Timestamp"]), d, r))
+    lines = [f"# {a.title}", f"# command: {a.command}", f"kernel_sha: {kernel_sha()}"]
+    key = [k for k in per if a.kernel in k]
+    if len(key) != 1:
+        raise SystemExit(f"kernel key {a.kernel!r} matches {key}")
+    ev = sorted(per[key[0]])[-a.last:]
+    durs = [d for _, d, _ in ev]
+    r0 = ev[-1][2]
+    lines += [f"timed_kernel: {key[0]}",
+              f"timed_dispatches: {len(durs)} (the last {a.last})",
+              f"timed_avg_ns: {sum(durs) / len(durs):.0f}",
+              f"timed_min_ns: {min(durs)}", f"timed_max_ns: {max(durs)}",
+              f"grid: {r0['Grid_Size_X']} x {r0['Grid_Size_Y']}, workgroup {r0['Workgroup_Size_X']}, "
+              f"VGPRs {r0['VGPR_Count']}, SGPRs {r0['SGPR_Count']}, LDS {r0['LDS_Block_Size']} B, "
+              f"scratch {r0['Scratch_Size']} B"]
+    lines.append("# all kernels of the run: name | calls | avg_ns | min_ns | max_ns")
+    for name, v in sorted(per.items(), key=lambda kv: -sum(d for _, d, _ in kv[1])):
+        ds = [d for _, d, _ in v]
+        lines.append(f"# {name[:70]} | {len(ds)} | {sum(ds) / len(ds):.0f} | {min(ds)} | {max(ds)}")
+    open(a.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -154,10 +188,18 @@ def main():
     s.add_argument("--command", default="")
     s.add_argument("--alg-bytes", type=int, default=0)
     s.add_argument("--kernels", default="k_step",
-                   help="comma-separated kernel-name keys whose per-dispatch counters make one step")
+                   help="kernel-name keys (separated by commas, or by semicolons when a key "
+                        "holds a comma) whose per-dispatch counters make one step")
     s.add_argument("--schedule", default="", help="launch shape the run used (recorded)")
+    t = sub.add_parser("trace")
+    t.add_argument("--trace", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--kernel", required=True, help="key of the timed kernel's name")
+    t.add_argument("--last", type=int, required=True)
+    t.add_argument("--title", default="kernel trace")
+    t.add_argument("--command", default="")
     a = ap.parse_args()
-    cmd_run(a) if a.cmd == "run" else cmd_summarize(a)
+    {"run": cmd_run, "summarize": cmd_summarize, "trace": cmd_trace}[a.cmd](a)
 
 
 if __name__ == "__main__":
