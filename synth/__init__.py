@@ -11,7 +11,7 @@ from .spec import Problem, BC_PERIODIC, BC_WALLS, BC_RESERVOIR
 from .rng import splitmix64, uniform_pm
 from .fields import layered_density, flat_interface_density, droplet_density
 from .throats import (tetra_throat, c1_problem, c2_problem, throat_incircle, pc_ramp, GAMMA_LAPLACE,
-                      small_throat_problem, three_sphere_throat)
+                      small_throat_problem, three_sphere_throat, constriction_problem)
 from .packing import (dense_packing, regular_triangulation, interior_facets, packing_throats,
                       packed_sample)
 from .network import pore_network, pore_void_volume
@@ -20,7 +20,7 @@ from .membrane import membrane_sample
 __all__ = [
     "Problem", "BC_PERIODIC", "BC_WALLS", "BC_RESERVOIR", "splitmix64", "uniform_pm",
     "layered_density", "flat_interface_density", "droplet_density", "tetra_throat",
-    "c1_problem", "c2_problem", "small_throat_problem", "three_sphere_throat", "throat_incircle", "pc_ramp", "GAMMA_LAPLACE",
+    "c1_problem", "c2_problem", "small_throat_problem", "three_sphere_throat", "constriction_problem", "throat_incircle", "pc_ramp", "GAMMA_LAPLACE",
     "dense_packing", "regular_triangulation", "interior_facets", "packing_throats",
     "packed_sample", "pore_network", "pore_void_volume", "membrane_sample",
 ]

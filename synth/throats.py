@@ -8,7 +8,7 @@ import numpy as np
 
 from .fields import layered_density
 from .rng import uniform01
-from .spec import BC_RESERVOIR, BC_WALLS, Problem
+from .spec import BC_PERIODIC, BC_RESERVOIR, BC_WALLS, Problem
 
 
 def tetra_throat(centroid, edge, radii, jitter=None):
@@ -107,6 +107,30 @@ def three_sphere_throat(R=32.0, margin=6, seed=3, amp=1e-3, rho_in=2.0):
     p = Problem(nx=nx, ny=ny, nz=nz, bc=(BC_WALLS, BC_WALLS, BC_RESERVOIR), spheres=sph,
                 prism_ids=(0, 1, 2), rho_in_nw=rho_in, rho_out_w=2.0, z_front=margin,
                 probe=_probe_near((axis[0], axis[1], zt + 3)))
+    p.rho_init = layered_density(nx, ny, nz, p.z_front, p.rho_major, p.rho_minor, seed, amp)
+    return p
+
+
+def constriction_problem(nx=20, ny=3, nz=36, gap=6.0, zc=14, seed=5, amp=1e-3):
+    """A quasi-two-dimensional throat: a slab periodic in x and y (ny nodes
+    thick) holding a periodic row of spheres centred on its mid-plane at
+    z = zc, one per period nx, of radius (nx - gap)/2, so that a slit `gap`
+    lattice units wide (half-way walls) opens between neighbours.  Below and
+    above the row the slab is open from side to side, so no solid touches
+    either bath.  The non-wetting phase fills z <= 3 next to the inlet bath;
+    the probe sits on the slit's axis 5 nodes past its narrowest section, in
+    the open region beyond it.  Small enough for the oracle to drain in
+    seconds, with a genuine entry pressure near the two-dimensional Laplace
+    value 2 gamma / gap of a perfectly wetting slit."""
+    R = (nx - gap) / 2.0
+    yc = (ny - 1) / 2.0
+    xc = -0.5  # the slit is centred on x = (nx - 1) / 2
+    # the sphere and its periodic image, so that every node of the slab sees
+    # the solid it is nearest to
+    sph = np.array([[xc, yc, zc, R], [xc + nx, yc, zc, R]])
+    p = Problem(nx=nx, ny=ny, nz=nz, bc=(BC_PERIODIC, BC_PERIODIC, BC_RESERVOIR), spheres=sph,
+                rho_in_nw=2.0, rho_out_w=2.0, z_front=3,
+                probe=(int(round((nx - 1) / 2.0)), int(round(yc)), zc + 5))
     p.rho_init = layered_density(nx, ny, nz, p.z_front, p.rho_major, p.rho_minor, seed, amp)
     return p
 
