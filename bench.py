@@ -362,6 +362,60 @@ def surrogate_leg():
             "inference_rows_per_s": round(SG_INFER / t_inf, 1)}
 
 
+def surrogate_eval_leg(path, n_test=SG_TEST):
+    """The surrogate with stored weights (trained by surrogate_data on throats
+    drained by the batched LBM) on held-out throats of another packing at the
+    same resolution: the network alone, the network with LBM fallback, and
+    the plain batched LBM on the same throats, p_c^e error against the LBM."""
+    from paper_1906_04722_amd import surrogate_data
+    m, meta = surrogate_data.load(path)
+    res, sides, conv = meta["lu_per_unit_radius"], tuple(meta["sides"]), meta["conv"]
+    te, rins, _ = synth.packing_throats(n_throats=n_test, seed=6, res=res, side_range=sides,
+                                        amp=0)
+    te_pc = surrogate_data.ramps(rins)
+    t0 = time.perf_counter()
+    ref, _ = lbm.drain_batch(te, te_pc, **conv)
+    t_lbm = time.perf_counter() - t0
+    log(f"surrogate: {len(te)} held-out throats drained by the LBM ({t_lbm:.1f} s)")
+    t0 = time.perf_counter()
+    res_sg, info = m.pce(te, te_pc, threshold=SG_THRESHOLD, **conv)
+    t_sg = time.perf_counter() - t0
+    pref = np.array([r["pce"] for r in ref])
+    Fte, r_msp = surrogate.describe(te, with_scale=True)
+    mean, std = m.predict(Fte)
+    raw = mean[:, 0] / r_msp
+    ok = np.isfinite(pref) & np.isfinite(raw)
+    err_raw = np.abs(raw[ok] - pref[ok]) / pref[ok]
+    fin = np.isfinite(res_sg["pce"]) & np.isfinite(pref)
+    err = np.abs(res_sg["pce"][fin] - pref[fin]) / pref[fin]
+    acc = fin & ~res_sg["used_fallback"]
+    err_acc = np.abs(res_sg["pce"][acc] - pref[acc]) / pref[acc]
+    ok1 = int((err <= 0.01).sum())
+    rows = np.tile(Fte, (SG_INFER // len(Fte) + 1, 1))[:SG_INFER]
+    m.predict(rows[:4096])
+    t0 = time.perf_counter()
+    m.predict(rows)
+    t_inf = time.perf_counter() - t0
+    m.close()
+    return {"workload": f"weights trained on {meta['trained_on']} of {meta['throats']} throats "
+                        f"of packing seed {meta['packing_seed']} drained by the batched LBM "
+                        f"({res:g} lu per unit radius, sides {sides[0]}-{sides[1]}, 16-point ramp, "
+                        f"cap {conv['max_steps']}); {len(te)} held-out throats of packing seed 6",
+            "recipe": meta, "test_throats": len(te), "threshold": SG_THRESHOLD,
+            "network_err_median": round(float(np.median(err_raw)), 4),
+            "network_within_1pct": round(float((err_raw <= 0.01).mean()), 4),
+            "network_within_5pct": round(float((err_raw <= 0.05).mean()), 4),
+            "fallback": int(info["n_fallback"]),
+            "fallback_rate": round(info["n_fallback"] / len(te), 4),
+            "accepted_err_median": round(float(np.median(err_acc)), 4) if acc.any() else None,
+            "final_err_median": round(float(np.median(err)), 4),
+            "final_within_1pct": ok1,
+            "throats_per_s_lbm": round(len(te) / t_lbm, 3),
+            "throats_per_s_surrogate_with_fallback": round(len(te) / t_sg, 3),
+            "within_1pct_per_s_surrogate_with_fallback": round(ok1 / t_sg, 3),
+            "inference_rows_per_s": round(SG_INFER / t_inf, 1)}
+
+
 def sample_setup():
     """The 512^3 packed sample on the GPU, its launch shape autotuned, and its
     drainage ramp begun (all before the timed region)."""
@@ -618,6 +672,9 @@ def main():
                     help="also run that packing fully resolved with the membrane (minutes)")
     ap.add_argument("--paper40", action="store_true",
                     help="also run the replica of the paper's 40-sphere sample (about 2 min)")
+    ap.add_argument("--sg-weights", default="",
+                    help="stored surrogate weights (surrogate_data train): evaluate them on "
+                         "held-out throats instead of training")
     ap.add_argument("--sg-train", type=int, default=SG_CFG["train"],
                     help="throats drained to train the surrogate (default 512, at most ~6000)")
     ap.add_argument("--schedule", default="",
@@ -710,7 +767,8 @@ def main():
     legs = [("batch", a.no_batch, lambda: batch_leg(a.batch_throats)),
             ("c2_96", a.no_c2, lambda: c2_leg(fixed)),
             ("dense_512", a.no_dense, dense_512),
-            ("surrogate", not a.surrogate, surrogate_leg),
+            ("surrogate", not a.surrogate or bool(a.sg_weights), surrogate_leg),
+            ("surrogate_stored", not a.sg_weights, lambda: surrogate_eval_leg(a.sg_weights)),
             ("three_sphere", not a.three, three_sphere_leg),
             ("hybrid_40", not (a.hybrid or a.full), hybrid_leg),
             ("full_40", not a.full, full_leg),

@@ -115,6 +115,7 @@ int sync_desc(lbm_throat *h) {
   T.list = h->list_d;
   T.nlist = h->nlist;
   T.rho = h->rho_d;
+  T.prog = tiled ? h->prog_d : nullptr;
   T.P = h->P;
   HIPCHK(hipMemcpyAsync(h->desc_d, &h->desc, sizeof(sc::Throat), hipMemcpyHostToDevice,
                         h->stream));
@@ -142,6 +143,25 @@ int rebuild_tiles(lbm_throat *h) {
   if (!list.empty())
     HIPCHK(hipMemcpyAsync(h->tiles_d, list.data(), sizeof(sc::TileRef) * list.size(),
                           hipMemcpyHostToDevice, h->stream));
+  // pacing words of the tile grid, all "not started" (the step only reads
+  // them as hints: results do not depend on them)
+  if (h->sched.tx != sc::kListTx) {
+    const size_t ng = (size_t)((h->nx + h->sched.tx - 1) / h->sched.tx) *
+                      ((h->ny + h->sched.ty - 1) / h->sched.ty) *
+                      ((h->nz + h->sched.lz - 1) / h->sched.lz);
+    if (ng > h->prog_cap) {
+      HIPCHK(hipStreamSynchronize(h->stream));
+      if (h->prog_d) (void)hipFree(h->prog_d);
+      h->prog_d = nullptr;
+      h->prog_cap = 0;
+      if (hipMalloc((void **)&h->prog_d, sizeof(uint32_t) * ng) != hipSuccess) {
+        set_err("hipMalloc of the pacing words failed");
+        return LBM_ENOMEM;
+      }
+      h->prog_cap = ng;
+    }
+    HIPCHK(hipMemsetAsync(h->prog_d, 0xff, sizeof(uint32_t) * ng, h->stream));
+  }
   HIPCHK(hipStreamSynchronize(h->stream));
   return sync_desc(h);
 }
@@ -258,6 +278,7 @@ void release(lbm_throat *h) {
   if (h->chunk_count_d) (void)hipFree(h->chunk_count_d);
   if (h->desc_d) (void)hipFree(h->desc_d);
   if (h->tiles_d) (void)hipFree(h->tiles_d);
+  if (h->prog_d) (void)hipFree(h->prog_d);
   if (h->zper_d) (void)hipFree(h->zper_d);
   if (h->red_d) (void)hipFree(h->red_d);
   if (h->red_h) (void)hipHostFree(h->red_h);
@@ -304,44 +325,6 @@ int copy_state(lbm_throat *h, float *dst, const float *src) {
   HIPCHK(hipMemcpyAsync(dst, src, sizeof(float) * sc::pop_elems(h->nx, h->ny, h->nz),
                         hipMemcpyDeviceToDevice, h->stream));
   return LBM_OK;
-}
-
-// run until |S(t) - S(t - every)| < tol or the cap; returns the point status
-int run_to_steady(lbm_throat *h, const lbm_conv *c, double *S_end, long long *used,
-                  int *invaded) {
-  double r[5];
-  TRY(reduce_now(h, r));
-  double S_old = r[2], S_new = S_old;
-  long long n = 0;
-  int st = LBM_PT_NOT_CONVERGED;
-  for (;;) {
-    if (h->timing) HIPCHK(hipEventRecord(h->tev[0], h->stream));
-    TRY(run_steps(h, c->check_every));
-    if (h->timing) HIPCHK(hipEventRecord(h->tev[1], h->stream));
-    n += c->check_every;
-    TRY(reduce_now(h, r));
-    if (h->timing) {
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, h->tev[0], h->tev[1]));
-      h->timed_ms += ms;
-      h->timed_launches += c->check_every;
-    }
-    S_new = r[2];
-    if (!std::isfinite(S_new)) {
-      st = LBM_PT_NONFINITE;
-      break;
-    }
-    if (std::fabs(S_new - S_old) < c->tol) {
-      st = LBM_PT_CONVERGED;
-      break;
-    }
-    if (n >= c->max_steps) break;
-    S_old = S_new;
-  }
-  *S_end = S_new;
-  *used = n;
-  *invaded = r[4] > r[3] ? 1 : 0;
-  return st;
 }
 
 }  // namespace
@@ -1164,8 +1147,8 @@ bool get_ramp(File &F, HostRamp &R) {
   R.status.resize(n);
   ok = F.get_n(R.pc.data(), n) && F.get_n(R.S.data(), n);
   for (int i = 0; ok && i < n; ++i) {
-    int64_t st64;
-    int32_t st32;
+    int64_t st64 = 0;
+    int32_t st32 = 0;
     ok = F.get(st64) && F.get(st32);
     R.steps[i] = st64;
     R.status[i] = st32;

@@ -10,7 +10,6 @@
 
 namespace sg {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bf16 to_bf16(float f) {
@@ -28,13 +27,61 @@ __device__ __forceinline__ float dsilu(float z) {
 }
 
 // ---- contraction ----------------------------------------------------------
-// Block tile 64 x 64 of C, four waves of 32 x 32, K staged through LDS 32 at a
-// time.  Each wave issues 2 x 2 v_mfma_f32_16x16x16_bf16 per 16 of K.  Operand
-// layout of that instruction (64 lanes, 4 values each): lane l holds
-// A[l % 16][4 (l / 16) + i] and B[4 (l / 16) + i][l % 16]; the result
-// C[4 (l / 16) + i][l % 16].  Both tiles sit in LDS k-contiguous ([row][k]),
-// so every operand is one 8-byte LDS read.
-constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;
+// Block tile 64 x 64 of C, four waves of 32 x 32, K staged through LDS 64 at a
+// time.  Each wave issues 2 x 2 v_mfma_f32_16x16x32_bf16 (gfx950) per 32 of
+// K.  Operand layout of that instruction (64 lanes, 8 values each): lane l
+// holds A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16]; the result
+// C[4 (l / 16) + i][l % 16].  Both tiles sit in LDS k-contiguous ([row][k],
+// rows padded to 72 bf16 = 144 bytes), so every operand is one 16-byte LDS
+// read.  Staging moves 16 bytes (8 bf16) per load where the operand allows:
+// along k when it is k-contiguous (X W^T, D W), along the rows when it is
+// row-contiguous (the weight gradients D^T A), scattering the 8 values into
+// their k-contiguous LDS rows; other shapes fall back to one value per load.
+constexpr int BM = 64, BN = 64, BK = 64, LDK = BK + 8;
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// stage rows r0 .. r0+63 and k0 .. k0+63 of X(row, k) = X[row*srow + k*sk]
+// (nrow rows, K columns) into S[row - r0][k - k0], zero outside
+__device__ __forceinline__ void stage(bf16 (&S)[64][LDK], const bf16 *X, long long srow,
+                                      long long sk, int nrow, int K, int r0, int k0, int tid) {
+  const bool aligned = ((uintptr_t)X & 15u) == 0;
+  if (sk == 1 && aligned && (srow & 7) == 0 && (K & 7) == 0) {
+    // k-contiguous: 8 consecutive k of one row per load (K % 8 == 0: a group
+    // of 8 lies wholly inside or outside the matrix)
+#pragma unroll
+    for (int t = 0; t < (64 * BK / 8) / 256; ++t) {
+      const int v = tid + 256 * t, r = v / (BK / 8), c = (v % (BK / 8)) * 8;
+      const int row = r0 + r, k = k0 + c;
+      uint4 q = make_uint4(0u, 0u, 0u, 0u);
+      if (row < nrow && k < K) q = *(const uint4 *)(X + (long long)row * srow + k);
+      *(uint4 *)&S[r][c] = q;
+    }
+  } else if (srow == 1 && aligned && (sk & 7) == 0 && (nrow & 7) == 0) {
+    // row-contiguous: 8 consecutive rows of one k per load, scattered into
+    // the k-contiguous tile (nrow % 8 == 0: a group lies wholly inside or out)
+#pragma unroll
+    for (int t = 0; t < (64 * BK / 8) / 256; ++t) {
+      const int v = tid + 256 * t, c = v / (64 / 8), r = (v % (64 / 8)) * 8;
+      const int row = r0 + r, k = k0 + c;
+      uint4 q = make_uint4(0u, 0u, 0u, 0u);
+      if (row < nrow && k < K) q = *(const uint4 *)(X + (long long)k * sk + row);
+      const bf16 *e = (const bf16 *)&q;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) S[r + i][c] = e[i];
+    }
+  } else {
+    // one value per load; consecutive threads walk the contiguous index
+    const bool kc = sk == 1;
+#pragma unroll 4
+    for (int t = 0; t < (64 * BK) / 256; ++t) {
+      const int idx = tid + 256 * t;
+      const int r = kc ? idx / BK : idx % 64;
+      const int c = kc ? idx % BK : idx / 64;
+      const int row = r0 + r, k = k0 + c;
+      S[r][c] = (row < nrow && k < K) ? X[(long long)row * srow + (long long)k * sk] : (bf16)0;
+    }
+  }
+}
 
 __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
   __shared__ __attribute__((aligned(16))) bf16 As[BM][LDK];
@@ -45,7 +92,6 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
   const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
   const bf16 *A = g.A + (long long)z * g.saz;
   const bf16 *B = g.B + (long long)z * g.sbz;
-  const bool a_kc = g.sak == 1, b_kc = g.sbk == 1;
   v4f acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -53,37 +99,23 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
   for (int k0 = 0; k0 < g.K; k0 += BK) {
-    // stage: consecutive threads walk the operand's contiguous index
-#pragma unroll
-    for (int r = 0; r < (BM * BK) / 256; ++r) {
-      const int idx = tid + 256 * r;
-      const int i = a_kc ? idx / BK : idx % BM;
-      const int kk = a_kc ? idx % BK : idx / BM;
-      const int m = m0 + i, k = k0 + kk;
-      As[i][kk] = (m < g.M && k < g.K) ? A[(long long)m * g.sam + (long long)k * g.sak] : (bf16)0;
-    }
-#pragma unroll
-    for (int r = 0; r < (BN * BK) / 256; ++r) {
-      const int idx = tid + 256 * r;
-      const int j = b_kc ? idx / BK : idx % BN;
-      const int kk = b_kc ? idx % BK : idx / BN;
-      const int n = n0 + j, k = k0 + kk;
-      Bs[j][kk] = (n < g.N && k < g.K) ? B[(long long)k * g.sbk + (long long)n * g.sbn] : (bf16)0;
-    }
+    // A(m, k) rows m; B(k, n) staged as rows n
+    stage(As, A, g.sam, g.sak, g.M, g.K, m0, k0, tid);
+    stage(Bs, B, g.sbn, g.sbk, g.N, g.K, n0, k0, tid);
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 16) {
-      v4s a[2], b[2];
-      const int q = kk + 4 * (lane >> 4);
+    for (int kk = 0; kk < BK; kk += 32) {
+      v8bf a[2], b[2];
+      const int q = kk + 8 * (lane >> 4);
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = *(const v4s *)&As[wm + 16 * i + (lane & 15)][q];
+      for (int i = 0; i < 2; ++i) a[i] = *(const v8bf *)&As[wm + 16 * i + (lane & 15)][q];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = *(const v4s *)&Bs[wn + 16 * j + (lane & 15)][q];
+      for (int j = 0; j < 2; ++j) b[j] = *(const v8bf *)&Bs[wn + 16 * j + (lane & 15)][q];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
