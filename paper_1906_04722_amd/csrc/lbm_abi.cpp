@@ -115,7 +115,6 @@ int sync_desc(lbm_throat *h) {
   T.list = h->list_d;
   T.nlist = h->nlist;
   T.rho = h->rho_d;
-  T.prog = tiled ? h->prog_d : nullptr;
   T.P = h->P;
   HIPCHK(hipMemcpyAsync(h->desc_d, &h->desc, sizeof(sc::Throat), hipMemcpyHostToDevice,
                         h->stream));
@@ -143,25 +142,6 @@ int rebuild_tiles(lbm_throat *h) {
   if (!list.empty())
     HIPCHK(hipMemcpyAsync(h->tiles_d, list.data(), sizeof(sc::TileRef) * list.size(),
                           hipMemcpyHostToDevice, h->stream));
-  // pacing words of the tile grid, all "not started" (the step only reads
-  // them as hints: results do not depend on them)
-  if (h->sched.tx != sc::kListTx) {
-    const size_t ng = (size_t)((h->nx + h->sched.tx - 1) / h->sched.tx) *
-                      ((h->ny + h->sched.ty - 1) / h->sched.ty) *
-                      ((h->nz + h->sched.lz - 1) / h->sched.lz);
-    if (ng > h->prog_cap) {
-      HIPCHK(hipStreamSynchronize(h->stream));
-      if (h->prog_d) (void)hipFree(h->prog_d);
-      h->prog_d = nullptr;
-      h->prog_cap = 0;
-      if (hipMalloc((void **)&h->prog_d, sizeof(uint32_t) * ng) != hipSuccess) {
-        set_err("hipMalloc of the pacing words failed");
-        return LBM_ENOMEM;
-      }
-      h->prog_cap = ng;
-    }
-    HIPCHK(hipMemsetAsync(h->prog_d, 0xff, sizeof(uint32_t) * ng, h->stream));
-  }
   HIPCHK(hipStreamSynchronize(h->stream));
   return sync_desc(h);
 }
@@ -278,7 +258,6 @@ void release(lbm_throat *h) {
   if (h->chunk_count_d) (void)hipFree(h->chunk_count_d);
   if (h->desc_d) (void)hipFree(h->desc_d);
   if (h->tiles_d) (void)hipFree(h->tiles_d);
-  if (h->prog_d) (void)hipFree(h->prog_d);
   if (h->zper_d) (void)hipFree(h->zper_d);
   if (h->red_d) (void)hipFree(h->red_d);
   if (h->red_h) (void)hipHostFree(h->red_h);

@@ -102,7 +102,6 @@ int build_tiles(Batch &B, const sc::Sched &s) {
     B.th_h[t].ntx = tiled ? (x->nx + s.tx - 1) / s.tx : 0;
     B.th_h[t].nty = tiled ? (x->ny + s.ty - 1) / s.ty : 0;
     B.th_h[t].lz = s.lz;
-    B.th_h[t].prog = nullptr;  // no pacing words for the batch's shared tile grid
   }
   BCHK(hipStreamSynchronize(B.stream));
   if (B.tiles_d) (void)hipFree(B.tiles_d);

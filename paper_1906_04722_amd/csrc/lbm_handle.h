@@ -71,8 +71,6 @@ struct lbm_throat {
   sc::TileRef *tiles_d = nullptr;
   int ntiles = 0;
   size_t tiles_cap = 0;
-  uint32_t *prog_d = nullptr;        // pacing hints of the tiled step (one word per tile)
-  size_t prog_cap = 0;
   int *zper_d = nullptr;             // {0} on a z-periodic subdomain (ghost planes)
   int n_zper = 0;
   // event-timed step launches inside the drainage ramp

@@ -103,8 +103,6 @@ struct Throat {
   const uint2 *list;     // node-list path: non-solid nodes in storage order (index, mask word)
   uint32_t nlist;
   float2 *rho;           // node-list path: densities of the current step [N]
-  uint32_t *prog;        // tiled path: per tile (tix + ntx (tiy + nty tiz)) the last
-                         // plane it finished and the step's parity, or null
   Phys P;
 };
 

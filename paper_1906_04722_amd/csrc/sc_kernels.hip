@@ -24,16 +24,6 @@
 // (the tiled step, the node-list step, the export) rounds it identically.
 #pragma clang fp contract(on)
 
-#ifndef SC_PACE
-#define SC_PACE 0
-#endif
-#ifndef SC_PACE_LAG
-#define SC_PACE_LAG 1
-#endif
-#ifndef SC_PACE_SPIN
-#define SC_PACE_SPIN 64
-#endif
-
 namespace sc {
 
 // ---- D3Q19: rest; +x,-x,+y,-y,+z,-z; twelve edges, opposite pairs adjacent
@@ -375,31 +365,7 @@ __global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(3))) voi
   stage_m[tid] = mnxt;
   __syncthreads();
 
-#if SC_PACE
-  // pacing: the tiles above and below share their boundary rows' lines with
-  // this one (halo pulls); holding back (a bounded wait) while such a
-  // neighbour that has started this step lags by more than SC_PACE_LAG
-  // planes keeps them close enough for those lines to still be in L2.  The
-  // words are hints only: results never depend on them.
-  uint32_t *const prog = T.prog;
-  const uint32_t pmark = (uint32_t)parity << 31;
-#endif
   for (int Z = z0; Z < z1; ++Z) {
-#if SC_PACE
-    if (prog && tid == 0) {
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        const int yn = tiy + (nb ? 1 : -1);
-        if (yn < 0 || yn >= nty) continue;
-        const uint32_t *w = prog + (tix + ntx * (yn + nty * tiz));
-        for (int it = 0; it < SC_PACE_SPIN; ++it) {
-          const uint32_t v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if ((v & 0x80000000u) != pmark || (int)(v & 0x7fffffffu) >= Z - SC_PACE_LAG) break;
-          __builtin_amdgcn_s_sleep(4);
-        }
-      }
-    }
-#endif
     const bool ahead = Z + 2 <= z1;  // plane Z+2 is needed (density halo or next own)
     // 1-2. halo node of plane Z+2, then own node of plane Z+2 (left in flight)
     if (ahead && halo)
@@ -441,11 +407,6 @@ __global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(3))) voi
       }
     mcur = stage_m[tid];
     stage_m[tid] = mnxt;
-#if SC_PACE
-    if (prog && tid == 0)
-      __hip_atomic_store(prog + tr.tile, pmark | (uint32_t)Z, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-#endif
     // 5.
     __syncthreads();
   }
