@@ -134,6 +134,14 @@ def one_drain(p, pcs, schedule=None):
 
 
 def _cpu_model():
+    import subprocess
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True,
+                                   timeout=10).stdout.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
@@ -166,6 +174,34 @@ def _sample_crop(p, n=128):
     rho0 = synth.layered_density(n, n, n, -1, p.rho_major, p.rho_minor)
     return synth.Problem(nx=n, ny=n, nz=n, bc=(synth.BC_WALLS,) * 3, spheres=S[keep],
                          rho_init=rho0, probe=None)
+
+
+def _timed_oracle(prob, budget_s, batch=2):
+    """Whole oracle steps on prob for about budget_s; (fluid nodes, steps, s)."""
+    import oracle
+    o = oracle.Oracle(prob)
+    n_fluid = int((o.types() == oracle.FLUID).sum())
+    o.step(1)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        o.step(batch)
+        n += batch
+    return n_fluid, n, time.perf_counter() - t0
+
+
+def cpu_other_configs(budget_s=4.0):
+    """The oracle on the other workloads' shapes (all cores, a few seconds
+    each): the 40^3 throat, the 96^3 throat, two throats of the batched
+    packing; fluid-node MLUPS."""
+    out = {}
+    probs, _, _ = synth.packing_throats(n_throats=2, seed=3)
+    for name, pr in (("throat_40", synth.c1_problem()), ("throat_96", synth.c2_problem()),
+                     ("batch_throat_a", probs[0]), ("batch_throat_b", probs[1])):
+        nf, n, dt = _timed_oracle(pr, budget_s)
+        out[name] = {"nodes": pr.n_nodes, "fluid_nodes": nf, "steps": n, "seconds": round(dt, 2),
+                     "fluid_MLUPS": round(nf * n / dt / 1e6, 3)}
+    return out
 
 
 def cpu_baseline(p, budget_s=10.0):
@@ -201,6 +237,7 @@ def cpu_baseline(p, budget_s=10.0):
                       f"{runs['all']['steps']} steps on all cores and {runs['one']['steps']} on "
                       "one core, about 10 s each",
             "one_core_fluid_MLUPS": runs["one"]["fluid_MLUPS"], "runs": runs,
+            "other_workloads_all_cores": cpu_other_configs(),
             "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
 
 
