@@ -52,6 +52,7 @@ CONV = dict(tol=1e-6, check_every=100, max_steps=20000, bisect_rel=0.005)
 # sides 48-128, 16-point ramp, entry pressure bracketed to 1 %, all in one
 # lbm_drain_batch call
 BATCH_THROATS = 512
+BATCH_SINGLES = 4
 BATCH_N_PC = 16
 BATCH_CONV = dict(tol=1e-6, check_every=100, max_steps=600, bisect_rel=0.01)
 # learned surrogate: trained on throats of one packing drained by the batched
@@ -257,6 +258,17 @@ def batch_leg(n_throats=BATCH_THROATS):
     log(f"batch: {len(probs)} throats drained in {dt:.1f} s")
     ok = sum(1 for o in out if o["invaded_at"] >= 0 and not o["failed"]
              and (o["pce_hi"] - o["pce_lo"]) <= BATCH_CONV["bisect_rel"] * o["pce_hi"])
+    # the plain per-throat path on the same GPU: the first few of the same
+    # throats drained one at a time (lbm_drain_throat, autotuned), same results
+    t1 = time.perf_counter()
+    n_single, same = BATCH_SINGLES, 0
+    for k in range(n_single):
+        g = lbm.Throat(probs[k])
+        g.autotune(6)
+        r = g.drain(pcs[k], **BATCH_CONV)
+        g.close()
+        same += int(np.array_equal(r["S"], out[k]["S"]) and r["total_steps"] == out[k]["total_steps"])
+    dt1 = time.perf_counter() - t1
     st = np.concatenate([o["status"] for o in out])
     fl = info["fluid_updates"] / (info["wall_ms"] * 1e-3)
     gbs = fl * BYTES_PER_FLUID_NODE / 1e9
@@ -269,6 +281,7 @@ def batch_leg(n_throats=BATCH_THROATS):
             "throats": len(probs), "box_nodes": int(sum(p.n_nodes for p in probs)),
             "wall_s": round(dt, 2), "device_ms": round(info["wall_ms"], 1),
             "throats_per_s": round(len(probs) / dt, 3),
+            "invaded_within_ramp": int(sum(1 for o in out if o["invaded_at"] >= 0)),
             "pce_bracketed_1pct": ok, "bracketed_throats_per_s": round(ok / dt, 3),
             "failed": int(sum(o["failed"] for o in out)),
             "points_converged": int((st == lbm.LBM_PT_CONVERGED).sum()),
@@ -278,7 +291,10 @@ def batch_leg(n_throats=BATCH_THROATS):
             "frac_note": "fluid-node updates x 304 B over the device time of the whole drain "
                          "(steps, reductions, decisions, checkpoint copies)",
             "schedule": [info["tx"], info["ty"], info["lz"]], "graph_replays": info["replays"],
-            "lattice_steps": info["lattice_steps"]}
+            "lattice_steps": info["lattice_steps"],
+            "single_throat_drains": {"throats": n_single, "throats_per_s": round(n_single / dt1, 3),
+                                     "identical_to_batch": same,
+                                     "batch_speedup": round((len(probs) / dt) / (n_single / dt1), 2)}}
 
 
 def surrogate_leg():
