@@ -53,3 +53,25 @@ def test_batched_drains_match_the_oracle():
         assert b["invaded_at"] == o["invaded_at"] >= 1
         assert dS <= 1e-3
         assert abs(b["pce"] - o["pce"]) <= 0.01 * o["pce"]
+
+
+@pytest.mark.parametrize("name", ["slit_gap6", "tetra40_s2"])
+def test_single_drain_matches_the_oracle(name):
+    """lbm_drain_throat (the resumable host ramp run to its end) on a stored
+    case: the same bars as the batch."""
+    from paper_1906_04722_amd import lbm
+    stored = _stored()
+    if name not in stored:
+        pytest.skip(f"{name} not stored")
+    o = stored[name]
+    p, _ = drain_cases.case(name)
+    t = lbm.Throat(p)
+    t.autotune(4)
+    b = t.drain(np.array(o["pc"]), **drain_cases.CONV)
+    t.close()
+    dS = float(np.max(np.abs(np.array(o["S"]) - b["S"])))
+    print(f"{name}: invaded at {b['invaded_at']} (oracle {o['invaded_at']}), p_c^e {b['pce']:.6g} "
+          f"(oracle {o['pce']:.6g}), max |dS| {dS:.2e}", flush=True)
+    assert b["invaded_at"] == o["invaded_at"] >= 1
+    assert dS <= 1e-3
+    assert abs(b["pce"] - o["pce"]) <= 0.01 * o["pce"]
