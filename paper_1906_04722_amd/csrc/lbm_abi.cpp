@@ -1234,6 +1234,17 @@ int lbm_load(lbm_throat_t h, const char *path) {
     set_err("lbm_load: %s is truncated or corrupt", path);
     return LBM_EINVAL;
   }
+  // a ramp in progress must carry settings lbm_drain_begin would accept
+  if (R.phase != HostRamp::kIdle &&
+      (check_drain_args(h, R.pc.data(), (int)R.pc.size(), &R.c, "lbm_load") != LBM_OK ||
+       !(R.phase == HostRamp::kDone || R.point < (int)R.pc.size()))) {
+    set_err("lbm_load: %s holds a drainage ramp with invalid settings (corrupt file)", path);
+    return LBM_EINVAL;
+  }
+  if ((nbuf == 3) != (R.phase == HostRamp::kRamp || R.phase == HostRamp::kBisect)) {
+    set_err("lbm_load: %s is truncated or corrupt", path);
+    return LBM_EINVAL;
+  }
   if (nbuf == 3) TRY(ensure_checkpoints(h, "lbm_load"));
   // from here on the handle's state is overwritten
   const size_t n = sc::pop_elems(h->nx, h->ny, h->nz);

@@ -95,3 +95,35 @@ def test_load_refuses_another_subdomain(tmp_path):
     assert np.array_equal(b.f(), before)
     a.close()
     b.close()
+
+
+def test_load_refuses_a_ramp_with_corrupt_settings(tmp_path):
+    """A saved ramp whose convergence settings were damaged (check_every 0)
+    is refused with LBM_EINVAL and leaves the handle as it was."""
+    import struct
+    from paper_1906_04722_amd import lbm
+    p, pcs = _throat()
+    a = lbm.Throat(p)
+    a.drain_begin(pcs, **CONV)
+    a.drain_advance(200)
+    path = str(tmp_path / "ramp.lbm")
+    a.save(path)
+    a.close()
+    raw = bytearray(open(path, "rb").read())
+    # file layout: 112-byte header, inlet density, steps done, then the ramp:
+    # phase, point, number of points, tol, check_every, ...
+    phase, point, n = struct.unpack_from("<iii", raw, 128)
+    tol, every = struct.unpack_from("<di", raw, 140)
+    assert (phase, n, tol, every) == (1, len(pcs), CONV["tol"], CONV["check_every"])
+    assert 0 <= point < n
+    struct.pack_into("<i", raw, 148, 0)
+    bad = str(tmp_path / "bad.lbm")
+    open(bad, "wb").write(bytes(raw))
+    b = lbm.Throat(p)
+    b.step(7)
+    before = b.f()
+    with pytest.raises(lbm.LBMError) as e:
+        b.load(bad, n_pc=len(pcs))
+    assert e.value.code == lbm.LBM_EINVAL
+    assert np.array_equal(b.f(), before)
+    b.close()
