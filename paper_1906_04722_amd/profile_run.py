@@ -11,6 +11,9 @@ writer for the counter output.
   python3 -m paper_1906_04722_amd.profile_run trace --trace T.csv --kernel K --last N
       --out profiles/NAME.txt: per-kernel statistics of a kernel trace and the
       average of kernel K's last N dispatches (a benchmark's timed region).
+  python3 -m paper_1906_04722_amd.profile_run sq --counters C.csv --stats S.csv
+      --kernel K --workload W --schedule S --out profiles/NAME.txt: one row of
+      SQ counters (waves, lifetimes, instructions per wave) of kernel K.
   python3 -m paper_1906_04722_amd.profile_run summarize --stats S.csv
       --fetch F.csv --write W.csv --out profiles/NAME.txt --command "..."
       writes the per-step averages of the step kernels (the fused k_step, or
@@ -136,6 +139,50 @@ def cmd_summarize(a):
     print("\n".join(lines))
 
 
+SQ_COUNTERS = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY",
+               "SQ_INSTS_VALU", "SQ_INSTS_VMEM_RD")
+
+
+def cmd_sq(a):
+    """One row of the SQ-counter table: per-dispatch means of the step
+    kernel's wave count, lifetime (SQ_WAVE_CYCLES per wave, counted in units of
+    4 cycles at 2.4 GHz), vector ALU and vector-memory-read instructions per
+    wave, and the share of SIMD time that issues vector ALU work (one wave64
+    instruction taken as 4 cycles, 1024 SIMDs, the step time of a separate
+    kernel-trace run)."""
+    vals = {c: _per_kernel(a.counters, c) for c in SQ_COUNTERS}
+    keys = [k for k in vals["SQ_WAVES"] if a.kernel in k]
+    if len(keys) != 1:
+        raise SystemExit(f"kernel key {a.kernel!r} matches {keys}")
+    k = keys[0]
+    mean = {c: sum(vals[c][k]) / len(vals[c][k]) for c in SQ_COUNTERS}
+    step_ns = None
+    for r in csv.DictReader(open(a.stats)):
+        if a.kernel in r["Name"]:
+            step_ns = float(r["AverageNs"])
+    if step_ns is None:
+        raise SystemExit(f"kernel {a.kernel!r} not in {a.stats}")
+    waves = mean["SQ_WAVES"]
+    life_us = mean["SQ_WAVE_CYCLES"] / waves * 4 / 2.4e3
+    valu_share = mean["SQ_INSTS_VALU"] * 4 / (1024 * step_ns * 2.4)
+    new = not os.path.exists(a.out)
+    with open(a.out, "a") as f:
+        if new:
+            f.write(f"# {a.title}\n# command: {a.command}\n")
+            f.write("# lifetime_us reads SQ_WAVE_CYCLES / SQ_WAVES in units of 4 cycles at 2.4 GHz; "
+                    "simd_valu_share is SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x step time), the "
+                    "share of SIMD time spent issuing vector ALU instructions (one wave64 "
+                    "instruction taken as 4 cycles)\n")
+            f.write(f"kernel_sha: {kernel_sha()}\n")
+            f.write("# workload | schedule | kernel | waves | lifetime_us | valu_per_wave | "
+                    "vmem_rd_per_wave | wait_inst_any_per_wave_cycle | step_ms | simd_valu_share\n")
+        f.write(f"{a.workload} | {a.schedule} | {k[:40]} | {waves:.0f} | {life_us:.1f} | "
+                f"{mean['SQ_INSTS_VALU'] / waves:.0f} | {mean['SQ_INSTS_VMEM_RD'] / waves:.1f} | "
+                f"{mean['SQ_WAIT_INST_ANY'] / mean['SQ_WAVE_CYCLES']:.2f} | {step_ns / 1e6:.3f} | "
+                f"{valu_share:.2f}\n")
+    print(open(a.out).read())
+
+
 def cmd_trace(a):
     """Summary of a kernel trace: per-kernel statistics, and for one kernel
     the average of its last `last` dispatches (the timed region of a run
@@ -191,6 +238,15 @@ def main():
                    help="kernel-name keys (separated by commas, or by semicolons when a key "
                         "holds a comma) whose per-dispatch counters make one step")
     s.add_argument("--schedule", default="", help="launch shape the run used (recorded)")
+    q = sub.add_parser("sq")
+    q.add_argument("--counters", required=True, help="counter_collection.csv of a --pmc run of SQ_*")
+    q.add_argument("--stats", required=True, help="kernel_stats.csv of a kernel-trace run")
+    q.add_argument("--kernel", required=True)
+    q.add_argument("--workload", required=True)
+    q.add_argument("--schedule", required=True)
+    q.add_argument("--out", required=True)
+    q.add_argument("--title", default="SQ counters of the fused step")
+    q.add_argument("--command", default="")
     t = sub.add_parser("trace")
     t.add_argument("--trace", required=True)
     t.add_argument("--out", required=True)
@@ -199,7 +255,7 @@ def main():
     t.add_argument("--title", default="kernel trace")
     t.add_argument("--command", default="")
     a = ap.parse_args()
-    {"run": cmd_run, "summarize": cmd_summarize, "trace": cmd_trace}[a.cmd](a)
+    {"run": cmd_run, "summarize": cmd_summarize, "trace": cmd_trace, "sq": cmd_sq}[a.cmd](a)
 
 
 if __name__ == "__main__":

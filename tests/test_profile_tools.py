@@ -51,3 +51,28 @@ def test_traffic_is_taken_by_hash_and_schedule(tmp_path, monkeypatch):
     assert bench.read_traffic("k_step_c2_96_", (16, 8, 1)) is None   # taken on other code
     assert bench.read_traffic("k_step_c2_96_", (32, 4, 1)) is None   # no summary for this shape
     assert bench.read_traffic("k_step_sample_512", (-1, 0, 0)) is None   # another workload
+
+
+def test_sq_row_from_counter_and_trace_csv(tmp_path):
+    """The SQ summary row: per-dispatch means over the step kernel's
+    dispatches only, lifetimes in units of 4 cycles at 2.4 GHz, and the VALU
+    share of 1024 SIMDs over the traced step time."""
+    import argparse
+    from paper_1906_04722_amd import profile_run as pr
+    rows = ["Kernel_Name,Counter_Name,Counter_Value"]
+    vals = {"SQ_WAVES": (100, 300), "SQ_WAVE_CYCLES": (1.2e6, 3.6e6), "SQ_BUSY_CYCLES": (1, 1),
+            "SQ_WAIT_INST_ANY": (0.6e6, 1.8e6), "SQ_INSTS_VALU": (2e5, 4e5),
+            "SQ_INSTS_VMEM_RD": (1000, 5000)}
+    for c, (v1, v2) in vals.items():
+        rows += [f"k_step<32 8>,{c},{v1}", f"k_step<32 8>,{c},{v2}", f"k_copy,{c},7"]
+    counters = _write(tmp_path, "c.csv", "\n".join(rows) + "\n")
+    stats = _write(tmp_path, "s.csv", "Name,AverageNs\nk_step<32 8>,1000000\nk_copy,5\n")
+    out = str(tmp_path / "sq.txt")
+    pr.cmd_sq(argparse.Namespace(counters=counters, stats=stats, kernel="k_step", workload="w",
+                                 schedule="32,8,16", out=out, title="t", command="c"))
+    row = open(out).read().strip().splitlines()[-1].split(" | ")
+    assert row[0] == "w" and row[3] == "200"                       # mean waves per dispatch
+    assert abs(float(row[4]) - 2.4e6 / 200 * 4 / 2400) < 0.1        # lifetime, us
+    assert row[5] == "1500" and row[6] == "15.0"                   # VALU and VMEM per wave
+    assert row[7] == "0.50" and row[8] == "1.000"
+    assert abs(float(row[9]) - 3e5 * 4 / (1024 * 1e6 * 2.4)) < 0.006
