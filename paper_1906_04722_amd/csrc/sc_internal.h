@@ -14,6 +14,8 @@ namespace sc {
 // flag the directions k whose pull source x - e_k is solid or beyond a wall
 enum : uint32_t { kFluid = 0, kSolid = 1, kResIn = 2, kResOut = 3 };
 constexpr int kTypeShift = 24;
+// bits 1..18 of a mask word: link k is cut (x - e_k solid or beyond a wall)
+constexpr uint32_t kLinkBits = 0x7FFFEu;
 
 // Population storage of one buffer: shifted FP32 populations g = f - w_k
 // rho_ref, q = 19 c + k for component c and direction k.  Each z-plane is cut

@@ -150,11 +150,14 @@ __device__ __forceinline__ acc_t sum19(const float (&a)[19]) {
 
 // Density seen by the interaction sums at (X, Y, Z): zero on solid nodes and
 // beyond walls, the imposed value on bath nodes, Eq. 2 on fluid nodes.  With
-// KEEP, the pulled populations and the mask word are returned for the
+// KEEP, the pulled populations, the mask word and the two FP64 sums of the
+// shifted populations (zero unless the node is fluid) are returned for the
 // collision of this node.
 template <bool KEEP>
 __device__ __forceinline__ float2 density_at(const Dom &d, const Phys &P, int X, int Y, int Z,
-                                             float (&v)[2][19], uint32_t &mword) {
+                                             float (&v)[2][19], uint32_t &mword,
+                                             double (&ds)[2]) {
+  if (KEEP) ds[0] = ds[1] = 0.0;
   const long long n = node_of(d, X, Y, Z);
   if (n < 0) {
     if (KEEP) mword = kSolid << kTypeShift;
@@ -169,7 +172,9 @@ __device__ __forceinline__ float2 density_at(const Dom &d, const Phys &P, int X,
   int X2 = wrap(X, d.nx), Y2 = wrap(Y, d.ny), Z2 = wrap(Z, d.nz);
   if (KEEP) {
     pull(d, m, X2, Y2, Z2, v);
-    return make_float2((float)((acc_t)P.rho_ref + sum19(v[0])), (float)((acc_t)P.rho_ref + sum19(v[1])));
+    ds[0] = sum19(v[0]);
+    ds[1] = sum19(v[1]);
+    return make_float2((float)((acc_t)P.rho_ref + ds[0]), (float)((acc_t)P.rho_ref + ds[1]));
   } else {
     float t2[2][19];
     pull(d, m, X2, Y2, Z2, t2);
@@ -190,14 +195,14 @@ __device__ __forceinline__ float2 density_at(const Dom &d, const Phys &P, int X,
 // component's mass to FP64 rounding (the BGK update does so exactly), and
 // FP32 rounding of the weights (their FP32 sum is not exactly 1) cannot bias
 // the mass step after step.  Momenta are summed from opposite-pair
-// differences.
+// differences.  drd: the FP64 sums of each component's 19 shifted
+// populations, as density_at() took them when the node was pulled.
 __device__ __forceinline__ void collide(const Phys &P, uint32_t m, const float (&Sw)[3],
-                                        const float (&Sn)[3], float (&v)[2][19]) {
-  double drd[2];
+                                        const float (&Sn)[3], const double (&drd)[2],
+                                        float (&v)[2][19]) {
   float dr[2], rho[2], j[2][3];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    drd[c] = sum19(v[c]);
     dr[c] = (float)drd[c];
     rho[c] = (float)((double)P.rho_ref + drd[c]);
     float jx = 0.f, jy = 0.f, jz = 0.f;
@@ -213,7 +218,9 @@ __device__ __forceinline__ void collide(const Phys &P, uint32_t m, const float (
     j[c][1] = jy;
     j[c][2] = jz;
   }
+  // adhesion direction: zero (the same +0 the sum gives) when no link is cut
   float A[3] = {0.f, 0.f, 0.f};
+  if ((m & kLinkBits) != 0u)
 #pragma unroll
   for (int k = 1; k < 19; ++k) {
     const float s = (float)((m >> opp(k)) & 1u) * wf(k);
@@ -355,14 +362,16 @@ __global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(3))) voi
 
   float cur[2][19], nxt[2][19], hv[2][19];
   uint32_t mcur = 0, mnxt = 0, mh;
+  // FP64 population sums of the own node at planes Z, Z+1, Z+2 (for collide)
+  double dcur[2], dmid[2], dnxt[2], dh[2];
 
   // prologue: densities of planes z0-1 .. z0+1, populations of z0 and z0+1
-  ring[(z0 - 1) & 3][ty + 1][tx + 1] = density_at<false>(d, P, x, y, z0 - 1, hv, mh);
-  if (halo) ring[(z0 - 1) & 3][hy + 1][hx + 1] = density_at<false>(d, P, x0 + hx, y0 + hy, z0 - 1, hv, mh);
-  ring[z0 & 3][ty + 1][tx + 1] = density_at<true>(d, P, x, y, z0, cur, mcur);
-  if (halo) ring[z0 & 3][hy + 1][hx + 1] = density_at<false>(d, P, x0 + hx, y0 + hy, z0, hv, mh);
-  ring[(z0 + 1) & 3][ty + 1][tx + 1] = density_at<true>(d, P, x, y, z0 + 1, nxt, mnxt);
-  if (halo) ring[(z0 + 1) & 3][hy + 1][hx + 1] = density_at<false>(d, P, x0 + hx, y0 + hy, z0 + 1, hv, mh);
+  ring[(z0 - 1) & 3][ty + 1][tx + 1] = density_at<false>(d, P, x, y, z0 - 1, hv, mh, dh);
+  if (halo) ring[(z0 - 1) & 3][hy + 1][hx + 1] = density_at<false>(d, P, x0 + hx, y0 + hy, z0 - 1, hv, mh, dh);
+  ring[z0 & 3][ty + 1][tx + 1] = density_at<true>(d, P, x, y, z0, cur, mcur, dcur);
+  if (halo) ring[z0 & 3][hy + 1][hx + 1] = density_at<false>(d, P, x0 + hx, y0 + hy, z0, hv, mh, dh);
+  ring[(z0 + 1) & 3][ty + 1][tx + 1] = density_at<true>(d, P, x, y, z0 + 1, nxt, mnxt, dmid);
+  if (halo) ring[(z0 + 1) & 3][hy + 1][hx + 1] = density_at<false>(d, P, x0 + hx, y0 + hy, z0 + 1, hv, mh, dh);
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -374,9 +383,10 @@ __global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(3))) voi
     const bool ahead = Z + 2 <= z1;  // plane Z+2 is needed (density halo or next own)
     // 1-2. halo node of plane Z+2, then own node of plane Z+2 (left in flight)
     if (ahead && halo)
-      ring[(Z + 2) & 3][hy + 1][hx + 1] = density_at<false>(d, P, x0 + hx, y0 + hy, Z + 2, hv, mh);
+      ring[(Z + 2) & 3][hy + 1][hx + 1] = density_at<false>(d, P, x0 + hx, y0 + hy, Z + 2, hv, mh, dh);
     float2 rho_ahead = make_float2(0.f, 0.f);
-    if (ahead) rho_ahead = density_at<true>(d, P, x, y, Z + 2, nxt, mnxt);
+    dnxt[0] = dnxt[1] = 0.0;
+    if (ahead) rho_ahead = density_at<true>(d, P, x, y, Z + 2, nxt, mnxt, dnxt);
     // 3. collide plane Z
     if (own) {
       const uint32_t t = mcur >> kTypeShift;
@@ -390,7 +400,7 @@ __global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(3))) voi
           if (ey(k)) { Sw[1] += ey(k) > 0 ? a : -a; Sn[1] += ey(k) > 0 ? bb : -bb; }
           if (ez(k)) { Sw[2] += ez(k) > 0 ? a : -a; Sn[2] += ez(k) > 0 ? bb : -bb; }
         }
-        collide(P, mcur, Sw, Sn, cur);
+        collide(P, mcur, Sw, Sn, dcur, cur);
         store_node(d, x, y, Z, cur);
       } else if (t == kResIn || t == kResOut) {
         const int i = t == kResIn ? 0 : 1;
@@ -412,6 +422,10 @@ __global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(3))) voi
       }
     mcur = stage_m[tid];
     stage_m[tid] = mnxt;
+    dcur[0] = dmid[0];
+    dcur[1] = dmid[1];
+    dmid[0] = dnxt[0];
+    dmid[1] = dnxt[1];
     // 5.
     __syncthreads();
   }
@@ -599,6 +613,7 @@ __global__ __launch_bounds__(kListBlock) void k_step_list(const Throat *__restri
     for (int a = 0; a < 3; ++a) jp[a] = __shfl_xor(j[a], 1);
     const float rho0 = c == 0 ? rho : rho_p, rho1 = c == 0 ? rho_p : rho;
     float A[3] = {0.f, 0.f, 0.f};
+    if ((m & kLinkBits) != 0u)
 #pragma unroll
     for (int k = 1; k < 19; ++k) {
       const float s = (float)((m >> opp(k)) & 1u) * wf(k);
