@@ -208,7 +208,11 @@ int main(int argc, char **argv) {
     ++chunks;
     if (ckpt) {
       char tmp[4096];
-      snprintf(tmp, sizeof tmp, "%s.tmp", ckpt);
+      if (snprintf(tmp, sizeof tmp, "%s.tmp", ckpt) >= (int)sizeof tmp) {
+        fprintf(stderr, "lbm_drain: checkpoint path too long\n");
+        status = 1;
+        goto out;
+      }
       rc = lbm_save(h, tmp);
       if (rc < 0 || rename(tmp, ckpt) != 0) {
         status = rc < 0 ? fail("lbm_save", rc) : 2;
