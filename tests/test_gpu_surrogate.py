@@ -178,3 +178,31 @@ def test_predict_and_fallback_to_lbm():
         assert np.array_equal(out0["curve"][i], r["S"])
         assert (np.isnan(out0["pce"][i]) and np.isnan(r["pce"])) or out0["pce"][i] == r["pce"]
         assert out0["pce_std"][i] == 0.0
+
+
+def test_fit_from_drained_parts(tmp_path):
+    """surrogate_data fit: the union of .npz parts trains an ensemble whose
+    stored weights reload with the recipe (rows and throats of all parts)."""
+    import json
+    from paper_1906_04722_amd import surrogate, surrogate_data
+    rng = np.random.default_rng(3)
+    files = []
+    for k, (first, rows, drained) in enumerate(((0, 30, 50), (50, 20, 40))):
+        recipe = dict(throats_in_list=90, packing_spheres=40, packing_seed=1, first=first,
+                      drained=drained, usable=rows, lu_per_unit_radius=8.0, sides=[24, 32],
+                      ramp_points=16, conv=dict(tol=1e-6, check_every=100, max_steps=200,
+                                                bisect_rel=0.01), lbm_seconds=1.5)
+        f = str(tmp_path / f"part{k}.npz")
+        np.savez(f, F=rng.normal(size=(rows, surrogate.NFEAT)),
+                 T=rng.normal(size=(rows, surrogate.NOUT)), recipe=np.array(json.dumps(recipe)))
+        files.append(f)
+    out = str(tmp_path / "w.safetensors")
+    import argparse
+    surrogate_data.cmd_fit(argparse.Namespace(data=files, epochs=2, batch=16, lr=1e-3, members=2,
+                                              out=out), print)
+    m, meta = surrogate_data.load(out)
+    assert meta["throats"] == 90 and meta["trained_on"] == 50 and meta["parts"] == [[0, 50], [50, 40]]
+    assert m.members == 2
+    y = m.predict(rng.normal(size=(5, surrogate.NFEAT)))[0]
+    assert np.all(np.isfinite(y))
+    m.close()
