@@ -728,6 +728,8 @@ def main():
     ap.add_argument("--sg-weights", default="",
                     help="stored surrogate weights (surrogate_data train): evaluate them on "
                          "held-out throats instead of training")
+    ap.add_argument("--sg-test", type=int, default=SG_TEST,
+                    help="held-out throats of the stored-weights evaluation")
     ap.add_argument("--sg-train", type=int, default=SG_CFG["train"],
                     help="throats drained to train the surrogate (default 512, at most ~6000)")
     ap.add_argument("--schedule", default="",
@@ -821,7 +823,7 @@ def main():
             ("c2_96", a.no_c2, lambda: c2_leg(fixed)),
             ("dense_512", a.no_dense, dense_512),
             ("surrogate", not a.surrogate or bool(a.sg_weights), surrogate_leg),
-            ("surrogate_stored", not a.sg_weights, lambda: surrogate_eval_leg(a.sg_weights)),
+            ("surrogate_stored", not a.sg_weights, lambda: surrogate_eval_leg(a.sg_weights, a.sg_test)),
             ("three_sphere", not a.three, three_sphere_leg),
             ("hybrid_40", not (a.hybrid or a.full), hybrid_leg),
             ("full_40", not a.full, full_leg),
