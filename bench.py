@@ -420,6 +420,8 @@ def surrogate_eval_leg(path, n_test=SG_TEST):
     drained by the batched LBM) on held-out throats of another packing at the
     same resolution: the network alone, the network with LBM fallback, and
     the plain batched LBM on the same throats, p_c^e error against the LBM."""
+    if not 1 <= n_test <= 512:
+        raise SystemExit("--sg-test: 1 to 512 held-out throats (one batch)")
     from paper_1906_04722_amd import surrogate_data
     m, meta = surrogate_data.load(path)
     res, sides, conv = meta["lu_per_unit_radius"], tuple(meta["sides"]), meta["conv"]
@@ -729,7 +731,8 @@ def main():
                     help="stored surrogate weights (surrogate_data train): evaluate them on "
                          "held-out throats instead of training")
     ap.add_argument("--sg-test", type=int, default=SG_TEST,
-                    help="held-out throats of the stored-weights evaluation")
+                    help="held-out throats of the stored-weights evaluation (at most 512: "
+                         "they are drained in one batch)")
     ap.add_argument("--sg-train", type=int, default=SG_CFG["train"],
                     help="throats drained to train the surrogate (default 512, at most ~6000)")
     ap.add_argument("--schedule", default="",
