@@ -175,10 +175,10 @@ def cmd_sq(a):
                     "instruction taken as 4 cycles)\n")
             f.write(f"kernel_sha: {kernel_sha()}\n")
             f.write("# workload | schedule | kernel | waves | lifetime_us | valu_per_wave | "
-                    "vmem_rd_per_wave | wait_inst_any_per_wave_cycle | step_ms | simd_valu_share\n")
+                    "vmem_rd_per_wave | wait_inst_any_per_wave_cycle | step_us | simd_valu_share\n")
         f.write(f"{a.workload} | {a.schedule} | {k[:40]} | {waves:.0f} | {life_us:.1f} | "
                 f"{mean['SQ_INSTS_VALU'] / waves:.0f} | {mean['SQ_INSTS_VMEM_RD'] / waves:.1f} | "
-                f"{mean['SQ_WAIT_INST_ANY'] / mean['SQ_WAVE_CYCLES']:.2f} | {step_ns / 1e6:.3f} | "
+                f"{mean['SQ_WAIT_INST_ANY'] / mean['SQ_WAVE_CYCLES']:.2f} | {step_ns / 1e3:.1f} | "
                 f"{valu_share:.2f}\n")
     print(open(a.out).read())
 

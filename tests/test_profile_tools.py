@@ -74,5 +74,5 @@ def test_sq_row_from_counter_and_trace_csv(tmp_path):
     assert row[0] == "w" and row[3] == "200"                       # mean waves per dispatch
     assert abs(float(row[4]) - 2.4e6 / 200 * 4 / 2400) < 0.1        # lifetime, us
     assert row[5] == "1500" and row[6] == "15.0"                   # VALU and VMEM per wave
-    assert row[7] == "0.50" and row[8] == "1.000"
+    assert row[7] == "0.50" and row[8] == "1000.0"
     assert abs(float(row[9]) - 3e5 * 4 / (1024 * 1e6 * 2.4)) < 0.006
