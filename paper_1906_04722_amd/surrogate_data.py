@@ -89,6 +89,8 @@ def load(path, seed=0):
 def cmd_drain(a, log):
     """One part of a training set: drained throats' descriptors and targets
     to an .npz (plain arrays and the recipe as JSON text)."""
+    if not a.out.endswith(".npz"):
+        raise SystemExit("drain --out: the part is an .npz file")
     sides = tuple(int(v) for v in a.sides.split(","))
     conv = dict(tol=1e-6, check_every=100, max_steps=a.cap, bisect_rel=0.01)
     t0 = time.perf_counter()
