@@ -55,6 +55,8 @@ BATCH_THROATS = 512
 BATCH_SINGLES = 4
 BATCH_N_PC = 16
 BATCH_CONV = dict(tol=1e-6, check_every=100, max_steps=600, bisect_rel=0.01)
+SAMPLE_PLACEMENTS = 3   # extra population-buffer pairs tried by lbm_place
+PLACEMENT = {}
 # learned surrogate: trained on throats of one packing drained by the batched
 # LBM, evaluated on throats of another packing against the plain LBM
 SG_TEST, SG_INFER = 256, 100000
@@ -477,6 +479,11 @@ def sample_setup():
     p, summ = synth.packed_sample(SAMPLE_N, SAMPLE_SPHERES, seed=4)
     g = lbm.Throat(p)
     sched = g.autotune(4)
+    # the step time depends on where the two population buffers lie in
+    # physical memory: keep the fastest of SAMPLE_PLACEMENTS + 1 pairs
+    ms0, ms1 = g.place(SAMPLE_PLACEMENTS, 4)
+    PLACEMENT.update(tries=SAMPLE_PLACEMENTS, first_pair_ms=round(ms0, 4), kept_pair_ms=round(ms1, 4))
+    log(f"placement: {ms0:.3f} ms per step on the first buffer pair, {ms1:.3f} on the kept one")
     n_fluid = int((g.types() == lbm.LBM_NODE_FLUID).sum())
     r_ins = (2.0 / np.sqrt(3.0) - 1.0) * summ["mean_radius_lu"]  # three touching spheres
     pcs = synth.pc_ramp(GAMMA, r_ins, SAMPLE_NPC)
@@ -803,6 +810,7 @@ def main():
         "box_MLUPS": round(p.n_nodes * lattice / dt / 1e6, 1),
         "lattice_steps_timed": int(lattice),
         "schedule": list(sched),
+        "placement": dict(PLACEMENT),
         "ramp": {"pc": [round(float(x), 6) for x in pcs],
                  "S_w_so_far": [round(float(x), 6) for x in ramp["S"]],
                  "status_so_far": [int(x) for x in ramp["status"]],

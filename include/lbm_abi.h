@@ -322,6 +322,21 @@ int lbm_set_schedule(lbm_throat_t h, int tx, int ty, int lz);
 int lbm_autotune(lbm_throat_t h, int trial_steps, int *tx, int *ty, int *lz);
 int lbm_get_schedule(lbm_throat_t h, int *tx, int *ty, int *lz);
 
+/* Placement of the two population buffers.  The step time of large,
+ * HBM-bound subdomains depends by several per cent on where the buffers lie
+ * in physical device memory, which an allocation cannot ask for.  This call
+ * times trial_steps steps (after 2 untimed ones) at the current launch shape
+ * on the current buffer pair and on up to `tries` (0..8) newly allocated
+ * pairs, each allocated while the earlier ones are still held; it keeps the
+ * fastest pair and frees the others.  As in lbm_autotune the trials run from
+ * a copy of the state that is put back into the kept pair, so the state is
+ * unchanged bit for bit.  *ms_first and *ms_best (either may be NULL)
+ * receive the per-step time of the original pair and of the kept one.
+ * Device memory while it runs: one population buffer for the copy plus two
+ * per try (LBM_ENOMEM if the memory budget refuses that; a try whose
+ * allocation fails ends the search without error).  Synchronous. */
+int lbm_place(lbm_throat_t h, int tries, int trial_steps, double *ms_first, double *ms_best);
+
 /* Stream-copy probe of the achievable HBM bandwidth (the measured roofline
  * denominator beside the 8 TB/s specification): copies `bytes` (>= 1 MiB)
  * between two device buffers `reps` times on the null stream and returns the

@@ -1399,6 +1399,108 @@ int lbm_autotune(lbm_throat_t h, int trial_steps, int *tx, int *ty, int *lz) {
   return LBM_OK;
 }
 
+int lbm_place(lbm_throat_t h, int tries, int trial_steps, double *ms_first, double *ms_best) {
+  if (!h || tries < 0 || tries > 8 || trial_steps < 1) {
+    set_err("lbm_place: bad handle, tries outside 0..8 or trial_steps < 1");
+    return LBM_EINVAL;
+  }
+  const size_t bytes = sizeof(float) * sc::pop_elems(h->nx, h->ny, h->nz);
+  TRY(lbmh::check_budget(bytes * (1 + 2 * (size_t)tries), "lbm_place"));
+  // The state is kept in a copy; each placement (the current pair, then
+  // `tries` new pairs allocated while the earlier ones are still held, so
+  // that they land elsewhere) runs 2 + trial_steps steps from that copy with
+  // alternating buffers, timed with events; the fastest pair gets the copy
+  // back and the others are freed, also on an error path.
+  struct Pair {
+    float *g[2] = {nullptr, nullptr};
+  };
+  struct Work {
+    lbm_throat *h;
+    float *keep = nullptr;
+    size_t bytes = 0;
+    Pair orig;
+    std::vector<Pair> cand;
+    int chosen = -1;  // -1: the original pair
+    ~Work() {
+      // the handle keeps the chosen pair; the copy goes back into it
+      if (chosen >= 0) {
+        h->g[0] = cand[chosen].g[0];
+        h->g[1] = cand[chosen].g[1];
+        h->cur = 0;
+      } else {
+        h->g[0] = orig.g[0];
+        h->g[1] = orig.g[1];
+      }
+      if (keep)
+        (void)hipMemcpyAsync(h->g[h->cur], keep, bytes, hipMemcpyDeviceToDevice, h->stream);
+      (void)sync_desc(h);
+      (void)hipStreamSynchronize(h->stream);
+      for (int i = 0; i < (int)cand.size(); ++i)
+        if (i != chosen)
+          for (float *b : cand[i].g)
+            if (b) (void)hipFree(b);
+      if (chosen >= 0)
+        for (float *b : orig.g) (void)hipFree(b);
+      if (keep) (void)hipFree(keep);
+    }
+  } w{h};
+  w.bytes = bytes;
+  w.orig.g[0] = h->g[0];
+  w.orig.g[1] = h->g[1];
+  if (hipMalloc((void **)&w.keep, bytes) != hipSuccess) {
+    w.keep = nullptr;
+    set_err("lbm_place: hipMalloc of %zu bytes for the state copy failed", bytes);
+    return LBM_ENOMEM;
+  }
+  HIPCHK(hipMemcpyAsync(w.keep, h->g[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream));
+  const int state0 = h->cur;
+  auto timed = [&](const Pair &pr, int parity, double *ms) -> int {
+    h->g[0] = pr.g[0];
+    h->g[1] = pr.g[1];
+    TRY(sync_desc(h));
+    HIPCHK(hipMemcpyAsync(pr.g[parity], w.keep, bytes, hipMemcpyDeviceToDevice, h->stream));
+    int par = parity;
+    auto one = [&]() {
+      const hipError_t e = sc::launch_step(h->desc_d, h->tiles_d, h->ntiles, h->sched.tx,
+                                           h->sched.ty, par, h->stream, h->zper_d, h->n_zper);
+      par ^= 1;
+      return e;
+    };
+    for (int i = 0; i < 2; ++i) HIPCHK(one());
+    HIPCHK(hipEventRecord(h->ev[0], h->stream));
+    for (int i = 0; i < trial_steps; ++i) HIPCHK(one());
+    HIPCHK(hipEventRecord(h->ev[1], h->stream));
+    HIPCHK(hipEventSynchronize(h->ev[1]));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, h->ev[0], h->ev[1]));
+    *ms = (double)t / trial_steps;
+    return LBM_OK;
+  };
+  double best = 0.0;
+  TRY(timed(w.orig, state0, &best));
+  const double first = best;
+  for (int k = 0; k < tries; ++k) {
+    Pair pr;
+    if (hipMalloc((void **)&pr.g[0], bytes) != hipSuccess ||
+        hipMalloc((void **)&pr.g[1], bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      if (pr.g[0]) (void)hipFree(pr.g[0]);
+      break;  // no room for another placement: keep the best so far
+    }
+    w.cand.push_back(pr);
+    double t = 0.0;
+    TRY(timed(pr, 0, &t));
+    if (t < best) {
+      best = t;
+      w.chosen = (int)w.cand.size() - 1;
+    }
+  }
+  if (w.chosen < 0) h->cur = state0;
+  if (ms_first) *ms_first = first;
+  if (ms_best) *ms_best = best;
+  return LBM_OK;
+}
+
 int lbm_get_schedule(lbm_throat_t h, int *tx, int *ty, int *lz) {
   if (!h) {
     set_err("NULL handle");

@@ -96,6 +96,7 @@ SIGNATURES = {
     "lbm_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "lbm_get_schedule": (ctypes.c_int, [ctypes.c_void_p, _ip, _ip, _ip]),
     "lbm_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _ip, _ip, _ip]),
+    "lbm_place": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp, _dp]),
     "lbm_bw_probe": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, _dp]),
     "lbm_step_timer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _llp]),
     "lbm_last_error": (ctypes.c_char_p, []),
@@ -318,6 +319,15 @@ class Throat:
         _check(lib().lbm_autotune(self.h, int(trial_steps), ctypes.byref(a), ctypes.byref(b),
                                   ctypes.byref(c)), "lbm_autotune")
         return a.value, b.value, c.value
+
+    def place(self, tries=2, trial_steps=4):
+        """Try `tries` more placements of the population buffers and keep the
+        fastest (lbm_place; state unchanged); returns (ms per step of the
+        original pair, of the kept one)."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(lib().lbm_place(self.h, int(tries), int(trial_steps), ctypes.byref(a),
+                               ctypes.byref(b)), "lbm_place")
+        return a.value, b.value
 
     def schedule(self):
         a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

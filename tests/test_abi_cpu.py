@@ -92,6 +92,9 @@ def test_invalid_arguments_rejected_without_gpu_work():
     P.bc[0] = lbm.LBM_BC_RESERVOIR
     assert L.lbm_throat_init(ctypes.byref(P), ctypes.byref(h)) == lbm.LBM_EINVAL
     assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
+    a, b = ctypes.c_double(-1.0), ctypes.c_double(-1.0)
+    assert L.lbm_place(None, 2, 4, ctypes.byref(a), ctypes.byref(b)) == lbm.LBM_EINVAL
+    assert (a.value, b.value) == (-1.0, -1.0)
     L.lbm_throat_free(None)
     del keep
 

@@ -127,3 +127,24 @@ def test_load_refuses_a_ramp_with_corrupt_settings(tmp_path):
     assert e.value.code == lbm.LBM_EINVAL
     assert np.array_equal(b.f(), before)
     b.close()
+
+
+def test_placement_search_keeps_the_state_bitwise():
+    """lbm_place moves the populations into the fastest of several buffer
+    pairs: the state is unchanged, and stepping on continues bit for bit as
+    in a handle that was never moved."""
+    from paper_1906_04722_amd import lbm
+    p = synth.c1_problem(seed=2)
+    a, b = lbm.Throat(p), lbm.Throat(p)
+    a.step(31)                # odd: the state sits in the second buffer
+    b.step(31)
+    before = a.f()
+    ms0, ms1 = a.place(3, 4)
+    print("placement", ms0, "->", ms1, flush=True)
+    assert 0 < ms1 <= ms0
+    assert np.array_equal(a.f(), before)
+    a.step(40)
+    b.step(40)
+    assert np.array_equal(a.f(), b.f())
+    a.close()
+    b.close()
