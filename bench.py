@@ -671,6 +671,7 @@ def dense_512(steps=10):
                       G_ads=(0.0, 0.0))
     g = lbm.Throat(p)
     sched = g.autotune(3)
+    ms0, ms1 = g.place(SAMPLE_PLACEMENTS, 3)
     g.step(2)
     g.sync()
     ms = g.time_steps(steps) / steps
@@ -678,6 +679,8 @@ def dense_512(steps=10):
     nodes = n ** 3
     gbs = nodes * BYTES_PER_FLUID_NODE / (ms * 1e-3) / 1e9
     return {"workload": "512^3 periodic fluid box", "schedule": list(sched),
+            "placement": {"tries": SAMPLE_PLACEMENTS, "first_pair_ms": round(ms0, 4),
+                          "kept_pair_ms": round(ms1, 4)},
             "ms_per_step": round(ms, 4),
             "MLUPS": round(nodes / ms / 1e3, 1), "achieved_GBps": round(gbs, 1),
             "peak_GBps": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4)}
