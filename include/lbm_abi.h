@@ -134,8 +134,8 @@ typedef struct {
 typedef struct lbm_throat *lbm_throat_t;
 
 /* Device-memory budget of the library's allocating calls, for callers that
- * share the GPU: with bytes > 0, lbm_throat_init, lbm_drain_throat and
- * lbm_drain_batch compute the device memory a call needs before allocating
+ * share the GPU: with bytes > 0, lbm_throat_init, lbm_drain_throat,
+ * lbm_drain_batch and lbm_place compute the device memory a call needs before allocating
  * anything (per subdomain: two population buffers of 152 bytes per padded
  * node, plus 25 bytes per node of masks, classes, densities and the node
  * list; two more population buffers for the ramp checkpoints of a drain) and
