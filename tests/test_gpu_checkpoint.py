@@ -148,3 +148,20 @@ def test_placement_search_keeps_the_state_bitwise():
     assert np.array_equal(a.f(), b.f())
     a.close()
     b.close()
+
+
+def test_placement_search_respects_the_memory_budget():
+    from paper_1906_04722_amd import lbm
+    p = synth.c1_problem(seed=2)
+    a = lbm.Throat(p)
+    a.step(5)
+    before = a.f()
+    lbm.set_memory_budget(1 << 20)     # far below one more population buffer
+    try:
+        with pytest.raises(lbm.LBMError) as e:
+            a.place(2, 4)
+        assert e.value.code == lbm.LBM_ENOMEM
+    finally:
+        lbm.set_memory_budget(0)
+    assert np.array_equal(a.f(), before)
+    a.close()
