@@ -55,7 +55,7 @@ BATCH_THROATS = 512
 BATCH_SINGLES = 4
 BATCH_N_PC = 16
 BATCH_CONV = dict(tol=1e-6, check_every=100, max_steps=600, bisect_rel=0.01)
-SAMPLE_PLACEMENTS = 3   # extra population-buffer pairs tried by lbm_place
+SAMPLE_PLACEMENTS = 4   # extra population-buffer pairs tried by lbm_place
 PLACEMENT = {}
 # learned surrogate: trained on throats of one packing drained by the batched
 # LBM, evaluated on throats of another packing against the plain LBM

@@ -317,7 +317,6 @@ __global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(3))) voi
   constexpr int NT = TX * TY;
   constexpr int H = 2 * (TX + 2) + 2 * TY;  // halo ring of one plane
   static_assert(NT >= H, "tile too small for its halo");
-  static_assert(NT % 64 == 0, "tiles are whole wavefronts");
   __shared__ float2 ring[4][TY + 2][TX + 2];
   __shared__ float stage[38][NT];
   __shared__ uint32_t stage_m[NT];
@@ -352,13 +351,11 @@ __global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(3))) voi
   const int z1 = min(z0 + lz, d.nz);
   const int x = x0 + tx, y = y0 + ty;
   const bool own = x < d.nx && y < d.ny;
-  // the H halo slots are spread evenly over the tile's wavefronts, so that
-  // no wavefront carries all of the halo's extra loads
-  constexpr int NW = NT / 64, HW = (H + NW - 1) / NW;
-  const int hidx = (tid >> 6) * HW + (tid & 63);
-  const bool halo = (tid & 63) < HW && hidx < H;
+  // the first H threads also pull one halo node each (the halo instructions
+  // are then issued by as few wavefronts as possible)
+  const bool halo = tid < H;
   int hx = 0, hy = 0;
-  if (halo) halo_slot<TX, TY>(hidx, hx, hy);
+  if (halo) halo_slot<TX, TY>(tid, hx, hy);
 
   float cur[2][19], nxt[2][19], hv[2][19];
   uint32_t mcur = 0, mnxt = 0, mh;
