@@ -76,3 +76,58 @@ def test_sq_row_from_counter_and_trace_csv(tmp_path):
     assert row[5] == "1500" and row[6] == "15.0"                   # VALU and VMEM per wave
     assert row[7] == "0.50" and row[8] == "1000.0"
     assert abs(float(row[9]) - 3e5 * 4 / (1024 * 1e6 * 2.4)) < 0.006
+
+
+def test_summarize_scales_counters_by_the_copy_calibration(tmp_path):
+    """Traffic per step: each counter's per-dispatch mean (KiB) scaled by the
+    factor that maps the copy kernel's reading onto the bytes it moves."""
+    import argparse
+    from paper_1906_04722_amd import profile_run as pr
+    gib = pr.COPY_BYTES / 1024.0                      # KiB the copy moves each way
+    rows = ["Kernel_Name,Counter_Name,Counter_Value"]
+    rows += [f"k_copy,FETCH_SIZE,{gib / 2}", f"k_copy,FETCH_SIZE,{gib / 2}"]   # reads half
+    rows += [f"k_step<32 8>,FETCH_SIZE,100", f"k_step<32 8>,FETCH_SIZE,300"]
+    fetch = _write(tmp_path, "f.csv", "\n".join(rows) + "\n")
+    rows = ["Kernel_Name,Counter_Name,Counter_Value", f"k_copy,WRITE_SIZE,{gib}",
+            "k_step<32 8>,WRITE_SIZE,50", "k_step<32 8>,WRITE_SIZE,50"]
+    write = _write(tmp_path, "w.csv", "\n".join(rows) + "\n")
+    stats = _write(tmp_path, "s.csv", "Name,Calls,AverageNs,MinNs,MaxNs,Percentage\n"
+                                      "k_step<32 8>,2,1000,900,1100,90\n")
+    out = str(tmp_path / "t.txt")
+    pr.cmd_summarize(argparse.Namespace(stats=stats, fetch=fetch, write=write, out=out,
+                                        title="t", command="c", alg_bytes=200 * 1024,
+                                        kernels="k_step", schedule="32,8,16"))
+    kv = dict(l.split(": ", 1) for l in open(out).read().splitlines() if ": " in l
+              and not l.startswith("#"))
+    assert float(kv["copy_fetch_scale"]) == 2.0 and float(kv["copy_write_scale"]) == 1.0
+    assert float(kv["fetch_bytes_per_launch"]) == 2.0 * 200 * 1024    # mean 200 KiB, x2
+    assert float(kv["write_bytes_per_launch"]) == 50 * 1024
+    assert float(kv["traffic_over_algorithmic"]) == 2.25
+
+
+def test_trace_averages_the_last_dispatches_of_one_kernel(tmp_path):
+    import argparse
+    from paper_1906_04722_amd import profile_run as pr
+    cols = ("Kernel_Name,Start_Timestamp,End_Timestamp,Grid_Size_X,Grid_Size_Y,Workgroup_Size_X,"
+            "VGPR_Count,SGPR_Count,LDS_Block_Size,Scratch_Size")
+    rows = [cols]
+    # three autotuner-like early dispatches of 50 ns, then four of 10 ns
+    t = 0
+    for d in (50, 50, 50, 10, 10, 10, 10):
+        rows.append(f"k_step<32 8>,{t},{t + d},256,1,256,160,100,51200,0")
+        t += 100
+    rows.append(f"k_copy,{t},{t + 7},1,1,256,8,16,0,0")
+    trace = _write(tmp_path, "t.csv", "\n".join(rows) + "\n")
+    out = str(tmp_path / "o.txt")
+    pr.cmd_trace(argparse.Namespace(trace=trace, out=out, kernel="k_step", last=4, title="t",
+                                    command="c"))
+    text = open(out).read()
+    assert "timed_avg_ns: 10\n" in text and "timed_dispatches: 4 (the last 4)" in text
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
