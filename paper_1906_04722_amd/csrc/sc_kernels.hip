@@ -236,15 +236,19 @@ __device__ __forceinline__ void collide(const Phys &P, uint32_t m, const float (
   }
   const float it0 = P.itau[0], it1 = P.itau[1];
   const float den = rho[0] * it0 + rho[1] * it1;
+  // quotients as products with three reciprocals (the node-list path below
+  // takes the same ones, so both paths stay bit-identical)
+  const float iden = 1.0f / den;
   float up[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) up[a] = (j[0][a] * it0 + j[1][a] * it1) / den;
+  for (int a = 0; a < 3; ++a) up[a] = (j[0][a] * it0 + j[1][a] * it1) * iden;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     float u[3];
     const float tc = P.tau[c], itc = P.itau[c];
+    const float irho = 1.0f / rho[c];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) u[a] = up[a] + tc * F[c][a] / rho[c];
+    for (int a = 0; a < 3; ++a) u[a] = up[a] + tc * F[c][a] * irho;
     const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     double rest = drd[c];
 #pragma unroll
@@ -624,16 +628,18 @@ __global__ __launch_bounds__(kListBlock) void k_step_list(const Throat *__restri
     for (int a = 0; a < 3; ++a) F[a] = -P.G * rho * So[a] - gads * rho * A[a];
     const float it0 = P.itau[0], it1 = P.itau[1];
     const float den = rho0 * it0 + rho1 * it1;
+    const float iden = 1.0f / den;
     float up[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const float j0 = c == 0 ? j[a] : jp[a], j1 = c == 0 ? jp[a] : j[a];
-      up[a] = (j0 * it0 + j1 * it1) / den;
+      up[a] = (j0 * it0 + j1 * it1) * iden;
     }
     const float tc = P.tau[c], itc = P.itau[c];
+    const float irho = 1.0f / rho;
     float u[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) u[a] = up[a] + tc * F[a] / rho;
+    for (int a = 0; a < 3; ++a) u[a] = up[a] + tc * F[a] * irho;
     const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     double rest = drd;
 #pragma unroll
